@@ -1,0 +1,34 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C-ABI library)")
+    config.addinivalue_line("markers", "slow: long CPU run; enabled with ESQ_SLOW=1")
+
+
+def pytest_collection_modifyitems(config, items):
+    if os.environ.get("ESQ_SLOW") == "1":
+        return
+    skip = pytest.mark.skip(reason="slow CPU pin; set ESQ_SLOW=1 to run")
+    for item in items:
+        if "slow" in item.keywords:
+            item.add_marker(skip)
+
+
+def read_golden(name):
+    """Rows of whitespace-separated ints/floats from tests/golden/<name>."""
+    rows = []
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            rows.append(line.split())
+    return rows
