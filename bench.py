@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the verification path on one MI355X.
+
+A step is one esq_verify_range call over the whole workload interval: the
+sieve of Algorithm 1 and the least-k search of Algorithm 2 over every odd n of
+the interval, with the aggregates (per-k counts, sum of k, maximum k,
+record-setters, exceptions) reduced on the device.  Inputs are the interval
+bounds; nothing is read from the host during the timed region.
+
+Prints one JSON line (rank 0, N = 1).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs at 2.4 GHz; 4 SIMD16 per CU -> 64 int32 lane-ops / clk / CU;
+# LDS 128 bytes / clk / CU.
+N_CU, CLK = 256, 2.4e9
+VALU_PEAK = N_CU * 64 * CLK          # 3.93e13 lane-ops/s
+LDS_PEAK = N_CU * 128 * CLK          # 7.86e13 B/s
+
+# Work of the bit-sliced method per odd n ("roofline"):
+#  LDS bytes: write the bitmap (1 bit), one 32-bit atomic OR per odd multiple
+#  of p^2 for p >= 13 (density sum_{p>=13} 1/p^2 = 0.02241), read the bitmap
+#  once (1 bit).
+LDS_BYTES_PER_N = 0.125 + 4 * 0.02241 + 0.125
+#  VALU lane-ops: 6 per search step per 64-n word (two funnel shifts, two ANDs,
+#  two popcounts) times the expected number of steps per word, 2.928, from the
+#  probabilities of Table 2 (1 + sum_k P(some of 64 n unresolved after k)).
+VALU_OPS_PER_N = 6 * 2.928 / 64
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(lo, hi, seconds, nthreads):
+    """The oracle, as it stands, on a bounded seeded sample of the workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2411_01964_amd import workloads
+
+    probe = workloads.random_odd(seed=3, count=max(2 * nthreads, 32), lo=lo, hi=hi)
+    oracle.mink_many(probe[:2], nthreads=1)  # builds the oracle's prime list
+    t0 = time.perf_counter()
+    oracle.mink_many(probe, nthreads=nthreads)
+    rate = len(probe) / max(time.perf_counter() - t0, 1e-9)
+    count = int(min(max(64, rate * seconds), 1 << 22))
+    sample = workloads.random_odd(seed=31, count=count, lo=lo, hi=hi)
+    t0 = time.perf_counter()
+    ks = oracle.mink_many(sample, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    assert int(np.count_nonzero(ks == 0)) == 0
+    return {
+        "value": count / dt,
+        "unit": "odd n/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": "%d seeded random odd n of the workload interval, trial division, %.1f s"
+                  % (count, dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg3_near_2pow50")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2411_01964_amd import esq, workloads
+
+    lo, hi = workloads.CONFIGS[args.workload]
+    n0 = max(lo, 3) | 1
+    n_odd = (hi - n0 + 1) // 2
+    log("init")
+    esq.init(0, hi + 64)
+    log("warmup x%d over %d odd n" % (args.warmup, n_odd))
+    ref = None
+    for _ in range(args.warmup):
+        ref = esq.verify_range(lo, hi)
+    esq.set_param("profile", 1)
+    esq.profile_take()
+    log("timed x%d" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pend = [esq.verify_range_async(lo, hi) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seg_ms, launches = esq.profile_take()
+    esq.set_param("profile", 0)
+    res = [p.result() for p in pend]
+    for r in res:
+        assert r["status"] == 0 and sum(r["hist"]) == n_odd
+        if ref is not None:
+            assert r["hist"] == ref["hist"] and r["records"] == ref["records"]
+    elapsed = t1 - t0
+    value = n_odd * args.steps / elapsed
+    log("%.3f s for %d steps -> %.4g odd n/s" % (elapsed, args.steps, value))
+
+    seg_avg_s = (seg_ms / max(launches, 1)) / 1e3
+    valu_ach = VALU_OPS_PER_N * n_odd / seg_avg_s
+    lds_ach = LDS_BYTES_PER_N * n_odd / seg_avg_s
+    roof_valu = {"bound": "alu", "achieved": valu_ach / 1e12, "peak": VALU_PEAK / 1e12,
+                 "unit": "Tlane-op/s", "frac": valu_ach / VALU_PEAK, "traffic": None,
+                 "kernel": "k_segment", "kernel_ms": seg_avg_s * 1e3}
+    roof_lds = {"bound": "lds", "achieved": lds_ach / 1e9, "peak": LDS_PEAK / 1e9,
+                "unit": "GB/s", "frac": lds_ach / LDS_PEAK, "traffic": None,
+                "kernel": "k_segment", "kernel_ms": seg_avg_s * 1e3}
+    roof, alt = (roof_valu, roof_lds) if roof_valu["frac"] >= roof_lds["frac"] else (roof_lds, roof_valu)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nthreads = min(16, os.cpu_count() or 1)
+        log("cpu baseline (oracle, %d threads, ~%.0f s)" % (nthreads, args.cpu_seconds))
+        cpu = cpu_baseline(lo, hi, args.cpu_seconds, nthreads)
+
+    r0 = res[0]
+    out = {
+        "metric": "odd n verified/sec near 2^50 (1 GPU)",
+        "value": value,
+        "unit": "odd n/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "every odd n in [%d, %d) (%s)" % (lo, hi, args.workload),
+            "n_odd": n_odd,
+            "seg_log2": esq.get_param("seg_log2"),
+            "kh": esq.get_param("kh"),
+            "block": esq.get_param("block"),
+        },
+        "roofline": roof,
+        "roofline_alt": alt,
+        "cpu_baseline": cpu,
+        "result": {"kmax_seen": r0["kmax_seen"], "ksum": r0["ksum"],
+                   "records": r0["records"], "n_exceptions": r0["n_exceptions"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * esq.h -- C-ABI of libesq, the MI355X (gfx950) library that verifies
+ * Erdos' conjecture "every odd n > 1 is a squarefree number plus a power of
+ * two" on whole intervals of odd integers, after C. Hercher, "On the Sum of
+ * Squarefree Integers and a Power of Two", arXiv 2411.01964.
+ *
+ * The signatures follow the paper's statement of the two algorithms:
+ *   Algorithm 1 (Section 3): input start, end; output, for every odd number
+ *     in [start, end), whether it is squarefree        -> esq_sieve_segment
+ *   Algorithm 2 (Section 3): input start, end, k_max; output, for every odd n
+ *     in [start, end), the least k >= 1 with n - 2^k squarefree, and a report
+ *     of every n with no such k                         -> esq_verify_range
+ *   "Collecting the results" (Section 3): aggregates instead of per-n arrays
+ *     (maximum k, sum of k), and the per-k counts and record-setters of
+ *     Section 4 (Tables 3 and 4)                        -> esq_summary
+ *
+ * Conventions shared by every entry point
+ *   - Ranges are half-open, [lo, hi).  Odd numbers only.  esq_verify_range
+ *     examines the odd n >= 3 (the conjecture concerns n > 1); the candidate
+ *     m = n - 2^k must satisfy m >= 1, i.e. 2^k < n, and k >= 1 (k = 0 is
+ *     excluded, so m is odd).  1 counts as squarefree.
+ *   - Device memory: every pointer argument marked "device" must be
+ *     device-accessible memory (hipMalloc'd, a torch CUDA tensor, or pinned
+ *     host memory from hipHostMalloc).  The caller owns and frees every
+ *     output buffer; the library never frees caller memory.  The library owns
+ *     the resident prime table, the pattern table and per-call scratch
+ *     (allocated and released in stream order on the caller's stream).
+ *   - Asynchrony: calls only enqueue work on `stream` (a hipStream_t; NULL =
+ *     the default stream) and return.  Outputs are valid once the stream has
+ *     been synchronised.  Calls on different streams may overlap.
+ *   - Errors: 0 on success, a negative ESQ_E* code otherwise (nothing is
+ *     enqueued then); esq_last_error() gives a message for the calling thread.
+ *     Conditions that only the device can see are reported in
+ *     esq_summary.status (ESQ_STATUS_* bits) once the stream has finished.
+ */
+#ifndef ESQ_H
+#define ESQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define ESQ_OK 0
+#define ESQ_EINVAL (-1)    /* bad argument (null required pointer, kmax > 63, lo > hi, ...) */
+#define ESQ_ERANGE (-2)    /* hi above the bound given to esq_init */
+#define ESQ_ENOMEM (-3)    /* device or host allocation failed */
+#define ESQ_EHIP (-4)      /* a HIP runtime call failed */
+#define ESQ_ENOINIT (-5)   /* esq_init has not been called (or failed) */
+
+/* esq_summary.status bits, set by the device */
+#define ESQ_STATUS_TAIL_OVERFLOW 1u  /* more unresolved n than the tail capacity:
+                                        counts past the in-LDS depth and the
+                                        exception list are incomplete */
+#define ESQ_STATUS_BUCKET_OVERFLOW 2u /* internal bound on large-prime hits
+                                         exceeded (never expected) */
+
+#define ESQ_MAX_HI (((uint64_t)1) << 56) /* largest hi accepted by esq_init */
+#define ESQ_RECORDS_CAP 64               /* capacity of out_records per call */
+#define ESQ_EXCEPTIONS_CAP_MAX 16384     /* largest exceptions_cap accepted */
+
+/* A record-setter (Table 3 of Section 4): an odd n whose least k is strictly
+ * larger than the least k of every smaller odd n of the same call.  An n with
+ * no representation counts as deeper than any k: it is reported once, with
+ * k = 0, and no later n of the call can be a record. */
+typedef struct esq_record {
+    uint64_t n;
+    uint32_t k;        /* least k, or 0 for an n with no representation */
+    uint32_t reserved; /* 0 */
+} esq_record;
+
+/* Aggregates of one call ("Collecting the results", Section 3; Table 4). */
+typedef struct esq_summary {
+    uint64_t n0;           /* first odd n examined (>= 3); 0 if none */
+    uint64_t n_odd;        /* number of odd n examined */
+    uint64_t hist[65];     /* hist[k] = #n with least k (1..63); hist[0] = #n with none */
+    uint64_t ksum;         /* sum of least k over the n that have one */
+    uint32_t kmax_seen;    /* largest least k found (0 if none) */
+    uint32_t n_records;    /* number of record-setters (<= ESQ_RECORDS_CAP) */
+    uint64_t n_exceptions; /* = hist[0]; may exceed the exceptions capacity */
+    uint32_t status;       /* ESQ_STATUS_* bits; 0 = complete and exact */
+    uint32_t reserved;
+} esq_summary;
+
+/*
+ * Select HIP device `device` and make the library resident on it: the odd
+ * primes p <= isqrt(max_hi) (Algorithm 1's prime list, Section 3) and the
+ * periodic pattern of odd multiples of 9, 25, 49 and 121.  Idempotent; a
+ * larger max_hi extends the table.  max_hi <= ESQ_MAX_HI.  Synchronous.
+ */
+int esq_init(int device, uint64_t max_hi);
+
+/*
+ * Algorithm 1 (Section 3) alone: squarefree flags of the odd m in [lo, hi).
+ * d_bits (device, caller-owned) receives ceil(n/64) little-endian uint64
+ * words, n = number of odd m in [max(lo,1), hi): bit i (LSB first) of the
+ * stream is 1 iff m0 + 2i is squarefree, m0 = first odd >= max(lo, 1).  Bits
+ * past the last m are 0.  hi <= the max_hi given to esq_init.
+ */
+int esq_sieve_segment(uint64_t lo, uint64_t hi, uint64_t *d_bits, void *stream);
+
+/*
+ * Algorithm 2 (Section 3) over every odd n in [lo, hi) with n >= 3, and the
+ * aggregates of "Collecting the results".
+ *   kmax           search limit: k runs 1, 2, ... while 2^k < n and
+ *                  (kmax == 0 or k <= kmax).  0 = no limit other than
+ *                  positivity.  kmax <= 63.
+ *   d_out_mink     device, nullable; n_odd bytes: [i] = least k of n0 + 2i,
+ *                  0 where none was found.
+ *   out_summary    device, required: one esq_summary.
+ *   out_records    device, nullable: ESQ_RECORDS_CAP entries; the first
+ *                  n_records are the record-setters in ascending n.
+ *   out_exceptions device, nullable when exceptions_cap == 0: the smallest
+ *                  min(exceptions_cap, n_exceptions) n with no representation,
+ *                  ascending.  exceptions_cap <= ESQ_EXCEPTIONS_CAP_MAX.
+ * Every count in the summary is exact unless status says otherwise.
+ */
+int esq_verify_range(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t *d_out_mink,
+                     esq_summary *out_summary, esq_record *out_records,
+                     uint64_t *out_exceptions, uint64_t exceptions_cap, void *stream);
+
+/*
+ * Tuning knobs (results never depend on them; only speed does).  Names:
+ *   "seg_log2"   log2 of the segment length in odd numbers held in LDS (10..20)
+ *   "kh"         deepest k resolved from the LDS bitmap (1..13); deeper k go
+ *                to the exact tail pass
+ *   "block"      threads per workgroup of the segment kernel (64..1024, x64)
+ *   "entry_hits" target marks per lane-task for medium primes (1..4096)
+ *   "tail_cap"   capacity of the per-call list of n unresolved in LDS
+ *   "profile"    1 = time each segment-kernel launch (esq_profile_take)
+ * Applies to calls made after it.  Returns ESQ_EINVAL for an unknown name
+ * or a value out of range.
+ */
+int esq_set_param(const char *name, int64_t value);
+int64_t esq_get_param(const char *name); /* -1 for an unknown name */
+
+/*
+ * Kernel timing for measurement.  While the knob "profile" is 1, every call
+ * records a pair of HIP events on its own stream around its segment-kernel
+ * launch (the kernel that sieves and searches in LDS).  esq_profile_take
+ * waits for the recorded events, writes the summed kernel time in
+ * milliseconds and the number of launches since the previous take, and
+ * clears the record.  Host pointers.  Returns ESQ_EINVAL for null pointers.
+ */
+int esq_profile_take(double *total_ms, uint64_t *launches);
+
+/* Message for the last non-zero return on the calling thread ("" if none). */
+const char *esq_last_error(void);
+
+/* Release every device resource.  esq_init may be called again afterwards. */
+void esq_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESQ_H */

@@ -1,0 +1,215 @@
+"""Python binding of libesq (ctypes).  Argument marshalling only: every step of
+the computation runs in the HIP kernels behind the C-ABI of include/esq.h.
+PyTorch provides device memory and streams.
+
+There is no CPU fallback: if libesq.so has not been built, or no GPU is
+present, these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesq.so")
+
+ESQ_RECORDS_CAP = 64
+ESQ_EXCEPTIONS_CAP_MAX = 16384
+ESQ_MAX_HI = 1 << 56
+STATUS_TAIL_OVERFLOW = 1
+STATUS_BUCKET_OVERFLOW = 2
+
+# every function declared in include/esq.h
+EXPORTS = ("esq_init", "esq_sieve_segment", "esq_verify_range", "esq_set_param",
+           "esq_get_param", "esq_profile_take", "esq_last_error", "esq_shutdown")
+
+
+class Summary(ctypes.Structure):
+    _fields_ = [
+        ("n0", ctypes.c_uint64),
+        ("n_odd", ctypes.c_uint64),
+        ("hist", ctypes.c_uint64 * 65),
+        ("ksum", ctypes.c_uint64),
+        ("kmax_seen", ctypes.c_uint32),
+        ("n_records", ctypes.c_uint32),
+        ("n_exceptions", ctypes.c_uint64),
+        ("status", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class Record(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+SUMMARY_BYTES = ctypes.sizeof(Summary)
+RECORD_BYTES = ctypes.sizeof(Record)
+
+
+class EsqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libesq error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Load libesq.so (raises if it was not built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libesq.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        u64, u32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+        L.esq_init.argtypes = [ctypes.c_int, u64]
+        L.esq_init.restype = ctypes.c_int
+        L.esq_sieve_segment.argtypes = [u64, u64, vp, vp]
+        L.esq_sieve_segment.restype = ctypes.c_int
+        L.esq_verify_range.argtypes = [u64, u64, u32, vp, vp, vp, vp, u64, vp]
+        L.esq_verify_range.restype = ctypes.c_int
+        L.esq_set_param.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+        L.esq_set_param.restype = ctypes.c_int
+        L.esq_get_param.argtypes = [ctypes.c_char_p]
+        L.esq_get_param.restype = ctypes.c_int64
+        L.esq_profile_take.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.esq_profile_take.restype = ctypes.c_int
+        L.esq_last_error.restype = ctypes.c_char_p
+        L.esq_shutdown.restype = None
+        _lib = L
+        return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise EsqError(rc, lib().esq_last_error().decode())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def init(device: int = 0, max_hi: int = (1 << 50) + (1 << 32)):
+    """Make the library resident on `device` for ranges up to max_hi."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: libesq runs on the GPU only")
+    torch.cuda.set_device(device)
+    _check(lib().esq_init(int(device), int(max_hi)))
+
+
+def shutdown():
+    lib().esq_shutdown()
+
+
+def set_param(name: str, value: int):
+    _check(lib().esq_set_param(name.encode(), int(value)))
+
+
+def get_param(name: str) -> int:
+    return int(lib().esq_get_param(name.encode()))
+
+
+def profile_take():
+    """(total_ms, launches) of segment-kernel launches recorded while the knob
+    "profile" was 1, since the previous take."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_uint64(0)
+    _check(lib().esq_profile_take(ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
+
+
+def sieve_segment(lo: int, hi: int, out=None, stream=None):
+    """Algorithm 1 alone on the odd m in [lo, hi).  Returns (m0, n_bits,
+    words) with `words` an int64 device tensor holding the little-endian
+    uint64 bit stream (bit i set iff m0 + 2i is squarefree)."""
+    lo, hi = int(lo), int(hi)
+    m0 = max(lo, 1) | 1
+    n = (hi - m0 + 1) // 2 if hi > m0 else 0
+    nw = (n + 63) // 64
+    if out is None:
+        out = torch.empty(max(nw, 1), dtype=torch.int64, device="cuda")
+    elif out.numel() < nw or out.dtype != torch.int64 or not out.is_cuda:
+        raise ValueError("out must be an int64 CUDA tensor of >= %d words" % nw)
+    _check(lib().esq_sieve_segment(lo, hi, _ptr(out), _stream(stream)))
+    return m0, n, out[:nw]
+
+
+class Pending:
+    """Device buffers of one enqueued esq_verify_range call."""
+
+    def __init__(self, lo, hi, kmax, per_n, exceptions_cap, stream):
+        self.lo, self.hi, self.kmax = int(lo), int(hi), int(kmax)
+        n0 = max(self.lo, 3) | 1
+        self.n_odd = (self.hi - n0 + 1) // 2 if self.hi > n0 else 0
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.summary = torch.zeros(SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+        self.records = torch.zeros(ESQ_RECORDS_CAP * RECORD_BYTES, dtype=torch.uint8, device=dev)
+        self.exc_cap = int(exceptions_cap)
+        self.exceptions = (torch.zeros(self.exc_cap, dtype=torch.int64, device=dev)
+                           if self.exc_cap else None)
+        self.per_n = (torch.empty(max(self.n_odd, 1), dtype=torch.uint8, device=dev)
+                      if per_n else None)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().esq_verify_range(
+            self.lo, self.hi, self.kmax, _ptr(self.per_n), _ptr(self.summary),
+            _ptr(self.records), _ptr(self.exceptions), self.exc_cap,
+            ctypes.c_void_p(self.stream.cuda_stream)))
+        self.event = torch.cuda.Event()
+        self.event.record(self.stream)
+
+    def done(self) -> bool:
+        return self.event.query()
+
+    def result(self, check: bool = True) -> dict:
+        self.event.synchronize()
+        s = Summary.from_buffer_copy(bytes(self.summary.cpu().numpy().tobytes()))
+        recs_raw = self.records.cpu().numpy().tobytes()
+        nrec = min(s.n_records, ESQ_RECORDS_CAP)
+        recs = []
+        for i in range(nrec):
+            r = Record.from_buffer_copy(recs_raw[i * RECORD_BYTES:(i + 1) * RECORD_BYTES])
+            recs.append((int(r.n), int(r.k)))
+        nexc = min(int(s.n_exceptions), self.exc_cap)
+        exc = [int(x) for x in self.exceptions[:nexc].cpu().tolist()] if nexc else []
+        out = {
+            "n0": int(s.n0),
+            "n_odd": int(s.n_odd),
+            "hist": [int(x) for x in s.hist],
+            "ksum": int(s.ksum),
+            "kmax_seen": int(s.kmax_seen),
+            "n_records": int(s.n_records),
+            "records": recs,
+            "n_exceptions": int(s.n_exceptions),
+            "exceptions": exc,
+            "status": int(s.status),
+        }
+        if self.per_n is not None:
+            out["per_n"] = self.per_n[:self.n_odd]
+        if check and s.status:
+            raise EsqError(-100, "device status 0x%x for [%d, %d)" % (s.status, self.lo, self.hi))
+        return out
+
+
+def verify_range_async(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None) -> Pending:
+    """Enqueue Algorithm 2 over the odd n in [lo, hi); returns a Pending."""
+    return Pending(lo, hi, kmax, per_n, exceptions_cap, stream)
+
+
+def verify_range(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None, check=True) -> dict:
+    """Algorithm 2 over every odd n >= 3 in [lo, hi) plus the aggregates
+    (per-k counts, sum of k, maximum k, record-setters, exceptions).  With
+    per_n=True the result holds "per_n", a uint8 CUDA tensor of least k."""
+    return verify_range_async(lo, hi, kmax, per_n, exceptions_cap, stream).result(check=check)

@@ -1,0 +1,75 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function that include/esq.h declares; struct layouts agree with the header.
+No compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2411_01964_amd import esq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "esq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(esq_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = esq.lib()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(esq.EXPORTS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "esq.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(esq_summary), sizeof(esq_record),'
+        ' offsetof(esq_summary, ksum), offsetof(esq_summary, status), offsetof(esq_record, k));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(esq.Summary), ctypes.sizeof(esq.Record),
+                   esq.Summary.ksum.offset, esq.Summary.status.offset, esq.Record.k.offset]
+
+
+def test_calls_before_init_fail_cleanly():
+    L = esq.lib()
+    L.esq_shutdown()
+    rc = L.esq_verify_range(3, 100, 0, None, None, None, None, 0, None)
+    assert rc == -5  # ESQ_ENOINIT
+    assert b"esq_init" in L.esq_last_error()
+    rc = L.esq_sieve_segment(1, 100, None, None)
+    assert rc == -5
+
+
+def test_param_validation():
+    assert esq.get_param("seg_log2") >= 10
+    with pytest.raises(esq.EsqError):
+        esq.set_param("seg_log2", 25)
+    with pytest.raises(esq.EsqError):
+        esq.set_param("kh", 0)
+    with pytest.raises(esq.EsqError):
+        esq.set_param("block", 100)
+    with pytest.raises(esq.EsqError):
+        esq.set_param("no_such_knob", 1)
+    assert esq.get_param("no_such_knob") == -1
+    old = esq.get_param("kh")
+    esq.set_param("kh", 7)
+    assert esq.get_param("kh") == 7
+    esq.set_param("kh", old)
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The binding never imports the oracle."""
+    src = open(os.path.join(ROOT, "paper_2411_01964_amd", "esq.py")).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")

@@ -1,0 +1,102 @@
+"""GPU results at the full sizes of the workloads, in the launch configuration
+that bench.py times (default knobs, summary mode), checked against what the
+paper fixes (Tables 3 and 4), against the oracle on sampled n, and against
+properties that hold at any size."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_01964_amd import esq, workloads
+from tests.conftest import read_golden
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib_ready():
+    esq.init(0, (1 << 50) + (1 << 33))
+    for k, v in dict(seg_log2=18, kh=13, block=256, entry_hits=16, tail_cap=1 << 20).items():
+        esq.set_param(k, v)
+
+
+def table2():
+    rows = read_golden("table2_probabilities.txt")
+    # printed to 5 significant digits: keep the rounding half-unit
+    out = {}
+    for r in rows:
+        mant, ex = r[2].split("e")
+        out[int(r[0])] = (float(r[2]), 0.5 * 10.0 ** (int(ex) - (len(mant.replace(".", "")) - 1)))
+    out[1] = (8.0 / math.pi ** 2, 0.0)  # d_1 = 8 / pi^2 (Section 2)
+    return out
+
+
+def check_density(hist, N):
+    p = table2()
+    for k in range(1, 9):
+        pk, rnd = p[k]
+        mean = N * pk
+        sigma = math.sqrt(N * pk * (1 - pk))
+        assert abs(hist[k] - mean) <= 6 * sigma + N * rnd + 1, (k, hist[k], mean, sigma)
+
+
+def check_records_with_oracle(res):
+    """Each record-setter's depth recomputed by the oracle; depths increase."""
+    ns = [n for n, _ in res["records"]]
+    ks = [int(x) for x in oracle.mink_many(ns)]
+    assert ks == [k for _, k in res["records"]]
+    assert ks == sorted(ks) and len(set(ks)) == len(ks)
+    assert res["records"][0][0] == res["n0"]
+
+
+def test_table4_and_table3_below_2pow30_on_gpu():
+    g = esq.verify_range(3, 1 << 30)
+    for k, cnt in read_golden("table4_hist.txt"):
+        assert g["hist"][int(k)] == int(cnt), k
+    assert sum(g["hist"]) == (1 << 29) - 1
+    assert g["ksum"] == 652_756_698
+    t3 = [(int(n), int(m) + 1) for m, n in read_golden("table3_records.txt") if int(n) < (1 << 30)]
+    assert g["records"] == [(3, 1)] + t3
+    assert g["kmax_seen"] == 9 and g["n_exceptions"] == 0
+
+
+@pytest.mark.parametrize("name,sample", [("cfg2_2pow40", 4096), ("cfg3_near_2pow50", 1024)])
+def test_full_interval(name, sample):
+    lo, hi = workloads.CONFIGS[name]
+    g = esq.verify_range(lo, hi)                       # the benchmarked call
+    N = g["n_odd"]
+    assert N == (hi - (lo | 1) + 1) // 2
+    assert sum(g["hist"]) == N and g["status"] == 0 and g["n_exceptions"] == 0
+    assert g["ksum"] == sum(k * c for k, c in enumerate(g["hist"]))
+    assert g["kmax_seen"] == max(k for k in range(65) if g["hist"][k])
+    assert g["kmax_seen"] <= 13                        # Theorem 1
+    check_density(g["hist"], N)
+    check_records_with_oracle(g)
+    # the per-n mode over the same interval: same counts, sampled n vs oracle
+    p = esq.verify_range(lo, hi, per_n=True)
+    assert p["hist"] == g["hist"] and p["records"] == g["records"]
+    per_n = p["per_n"]
+    counts = torch.bincount(per_n, minlength=65).cpu().tolist()
+    assert counts[:65] == g["hist"]
+    ns = workloads.random_odd(seed=hash(name) & 0xffff, count=sample, lo=lo, hi=hi)
+    idx = torch.from_numpy(((ns - np.uint64(g["n0"])) // np.uint64(2)).astype(np.int64)).cuda()
+    got = per_n[idx].cpu().numpy()
+    assert np.array_equal(got, oracle.mink_many(ns))
+    # record-setters are where the running maximum of per_n increases
+    for n, k in g["records"]:
+        assert int(per_n[(n - g["n0"]) // 2]) == k
+    del per_n, p
+    torch.cuda.empty_cache()
+
+
+def test_full_interval_windows_vs_oracle():
+    """Seeded windows inside the benchmarked intervals, element by element."""
+    for name, width, seed in (("cfg2_2pow40", 1 << 13, 2), ("cfg3_near_2pow50", 1 << 10, 3)):
+        lo, hi = workloads.CONFIGS[name]
+        for a, b in workloads.random_windows(seed, 2, width, lo, hi):
+            g = esq.verify_range(a, b, per_n=True)
+            o = oracle.verify_range(a, b, per_n=True)
+            assert g["hist"] == o["hist"] and g["records"] == o["records"]
+            assert np.array_equal(g["per_n"].cpu().numpy(), o["per_n"])
