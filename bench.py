@@ -71,15 +71,94 @@ def cpu_baseline(lo, hi, seconds, nthreads):
     }
 
 
+def bench_batched(steps):
+    """Config 4: 4096 seeded intervals (lengths 2^16..2^28 odd n, starts in
+    [2^30, 2^50)) in one prepared batch replayed as a hipGraph, against the
+    plain path (one esq_verify_range per interval, back to back on one
+    stream).  Results must agree exactly."""
+    import torch
+
+    from paper_2411_01964_amd import esq, workloads
+
+    lo, hi = workloads.batch_intervals(seed=4, count=4096)
+    n_total = sum(((b - (max(a, 3) | 1) + 1) // 2) for a, b in zip(lo, hi))
+    pb = esq.PreparedBatch(lo, hi)
+    pb.launch(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pb.launch(graph=True)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    batched = pb.results()
+    pb.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pend = [esq.verify_range_async(a, b) for a, b in zip(lo, hi)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain = [p.result() for p in pend]
+    for x, y in zip(batched, plain):
+        assert x["hist"] == y["hist"] and x["records"] == y["records"]
+    return {"intervals": len(lo), "odd_n": n_total,
+            "batched_odd_n_per_s": n_total / t_batch, "batched_ms": t_batch * 1e3,
+            "plain_odd_n_per_s": n_total / t_plain, "plain_ms": t_plain * 1e3,
+            "speedup": t_plain / t_batch, "identical": True}
+
+
+def bench_served():
+    """Config 5: Poisson arrivals (2000 req/s, seeded), lengths 2^12..2^30
+    odd n, starts in [3, 2^50), half asking for per-n least k.  1 s warm-up
+    plus 10 s measured; p50/p99 latency from arrival to completion.  Then the
+    same requests all at once through the server (its capacity) and through
+    the plain path (one esq_verify_range per request, in order)."""
+    import torch
+
+    from paper_2411_01964_amd import esq, serve, workloads
+
+    reqs = workloads.poisson_requests(seed=5, rate=2000.0, duration=11.0)
+    _, wall, paced = serve.run_stream(reqs, n_streams=4, warmup_s=1.0, paced=True,
+                                      keep_per_n=False)
+    _, wall_u, unpaced = serve.run_stream(reqs, n_streams=4, warmup_s=0.0, paced=False,
+                                          keep_per_n=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_plain = 0
+    for _, a, b, per_n in reqs:
+        r = esq.verify_range(a, b, per_n=per_n)
+        n_plain += r["n_odd"]
+        del r
+    t_plain = time.perf_counter() - t0
+    return {"requests": paced["requests"], "offered_odd_n_per_s": paced["odd_n"] / 11.0,
+            "p50_ms": paced["p50_ms"], "p99_ms": paced["p99_ms"],
+            "served_paced_odd_n_per_s": paced["odd_n"] / wall,
+            "served_capacity_odd_n_per_s": unpaced["odd_n"] / wall_u,
+            "plain_odd_n_per_s": n_plain / t_plain, "batches": paced["batches"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg3_near_2pow50")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (4096 intervals) and served (Poisson) measurements")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied %d bytes" % args.copy_probe)
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,6 +214,13 @@ def main():
         log("cpu baseline (oracle, %d threads, ~%.0f s)" % (nthreads, args.cpu_seconds))
         cpu = cpu_baseline(lo, hi, args.cpu_seconds, nthreads)
 
+    extras = {}
+    if not args.no_extras:
+        log("batched: 4096 intervals")
+        extras["batched"] = bench_batched(steps=5)
+        log("served: Poisson stream, 11 s")
+        extras["served"] = bench_served()
+
     r0 = res[0]
     out = {
         "metric": "odd n verified/sec near 2^50 (1 GPU)",
@@ -159,6 +245,10 @@ def main():
         "roofline": roof,
         "roofline_alt": alt,
         "cpu_baseline": cpu,
+        "latency_p50_ms": extras.get("served", {}).get("p50_ms"),
+        "latency_p99_ms": extras.get("served", {}).get("p99_ms"),
+        "batched": extras.get("batched"),
+        "served": extras.get("served"),
         "result": {"kmax_seen": r0["kmax_seen"], "ksum": r0["ksum"],
                    "records": r0["records"], "n_exceptions": r0["n_exceptions"]},
     }

@@ -122,6 +122,47 @@ int esq_verify_range(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t *d_out_min
                      uint64_t *out_exceptions, uint64_t exceptions_cap, void *stream);
 
 /*
+ * Many intervals in one launch (the batched form of esq_verify_range): every
+ * interval [lo[i], hi[i]) is cut into segments, and persistent workgroups
+ * pull runs of consecutive segments of any interval from one device work
+ * queue, so short and long intervals share the GPU.  Results per interval are
+ * identical to esq_verify_range on that interval alone.
+ *   count          number of intervals
+ *   lo, hi         host arrays of count bounds (half-open, as above)
+ *   kmax           as in esq_verify_range, for every interval
+ *   d_out_mink     host array of count device pointers (entries may be NULL)
+ *                  receiving each interval's per-n least k; or NULL
+ *   out_summaries  device, required: count esq_summary
+ *   out_records    device, nullable: count * ESQ_RECORDS_CAP esq_record;
+ *                  interval i's records start at i * ESQ_RECORDS_CAP
+ * Exceptions are counted (hist[0]) but not listed.
+ */
+int esq_verify_batch(uint32_t count, const uint64_t *lo, const uint64_t *hi, uint32_t kmax,
+                     uint8_t *const *d_out_mink, esq_summary *out_summaries,
+                     esq_record *out_records, void *stream);
+
+/*
+ * Prepared batches: the same work as esq_verify_batch, planned once, with its
+ * scratch and descriptors kept on the device, so that it can be launched
+ * repeatedly without host planning, allocation or copies -- and captured as
+ * a hipGraph.
+ *   esq_batch_create   plans and allocates (synchronous); the output pointers
+ *                      are bound to the handle and rewritten by every launch.
+ *   esq_batch_launch   enqueues the kernels on `stream`; with use_graph != 0
+ *                      the kernel sequence is captured into a hipGraph on the
+ *                      first such launch and replayed afterwards.  Launches of
+ *                      one handle must not overlap in time (they share its
+ *                      scratch); different handles may run concurrently.
+ *   esq_batch_destroy  waits for the device and frees the handle.
+ */
+typedef struct esq_batch esq_batch;
+int esq_batch_create(uint32_t count, const uint64_t *lo, const uint64_t *hi, uint32_t kmax,
+                     uint8_t *const *d_out_mink, esq_summary *out_summaries,
+                     esq_record *out_records, esq_batch **out_handle);
+int esq_batch_launch(esq_batch *batch, int use_graph, void *stream);
+void esq_batch_destroy(esq_batch *batch);
+
+/*
  * Tuning knobs (results never depend on them; only speed does).  Names:
  *   "seg_log2"   log2 of the segment length in odd numbers held in LDS (10..20)
  *   "kh"         deepest k resolved from the LDS bitmap (1..13); deeper k go
@@ -130,6 +171,11 @@ int esq_verify_range(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t *d_out_min
  *   "entry_hits" target marks per lane-task for medium primes (1..4096)
  *   "tail_cap"   capacity of the per-call list of n unresolved in LDS
  *   "profile"    1 = time each segment-kernel launch (esq_profile_take)
+ *   "medium_max" largest prime whose multiples every segment marks itself
+ *                (11..11000); larger primes go through per-segment hit slots
+ *   "bucket_cap" hit slots per segment (0 = sized from the expected count);
+ *                a segment whose slots overflow marks those primes directly
+ *   "items_per_wg" batched form: work items per resident workgroup
  * Applies to calls made after it.  Returns ESQ_EINVAL for an unknown name
  * or a value out of range.
  */

@@ -2,8 +2,8 @@
 //
 // The library keeps, per process, one context on one device: the odd primes
 // up to isqrt(max_hi) (Algorithm 1's prime list, Section 3 of the paper), the
-// pattern table of odd multiples of 9, 25, 49 and 121, and cached lane-task
-// tables for the medium primes.  Each call plans its segments on the host,
+// pattern table of odd multiples of 9, 25, 49 and 121, and cached tables for
+// the medium primes.  Each call plans its intervals and segments on the host,
 // allocates scratch in stream order on the caller's stream, enqueues the
 // kernels and returns; nothing here waits for the device.
 #include <algorithm>
@@ -42,29 +42,34 @@ struct Params {
     int entry_hits = 16;
     int64_t tail_cap = 1 << 20;
     int profile = 0;
+    int64_t medium_max = 8191;  // largest prime marked per segment (others: hit slots)
+    int64_t bucket_cap = 0;     // hit slots per segment; 0 = from the expected count
+    int64_t items_per_wg = 4;   // batch: work items per resident workgroup
 };
 
 struct MedTable {
-    MedEntry* d = nullptr;
-    uint32_t n = 0;
+    MedTask* tasks = nullptr;
+    uint2* medq = nullptr;
+    uint32_t n_tasks = 0;
 };
 
 struct Ctx {
     int device = -1;
+    int n_cu = 256;
     uint64_t max_hi = 0;
     uint64_t plimit = 0;            // every odd prime <= plimit is in `primes`
     std::vector<uint32_t> primes;   // odd primes ascending (3, 5, 7, ...)
     std::vector<double> inv_pref;   // inv_pref[i] = sum over t < i of 1 / primes[t]^2
     uint32_t* d_primes = nullptr;
     uint64_t* d_wheel = nullptr;
-    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, MedTable> med;
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
 };
 
 std::mutex g_mu;
 Ctx* g_ctx = nullptr;
 Params g_par;
 
-// event pairs recorded around segment-kernel launches while "profile" is on
+// event pairs recorded around verify-kernel launches while "profile" is on
 std::mutex g_prof_mu;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_open, g_prof_pool;
 
@@ -95,10 +100,77 @@ void prof_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t>& ev)
     g_prof_open.push_back(ev);
 }
 
+// Pinned host staging buffers for descriptor uploads: a buffer is reused only
+// once the event recorded after its last copy has completed.
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool taken = false;
+};
+std::mutex g_stage_mu;
+std::vector<Staging> g_stage;
+
+int stage_upload(const std::vector<std::pair<const void*, size_t>>& parts,
+                 const std::vector<char*>& dsts, hipStream_t s)
+{
+    size_t total = 0;
+    for (auto& p : parts)
+        total += (p.second + 255) & ~(size_t)255;
+    if (total == 0)
+        return ESQ_OK;
+    int idx = -1;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        for (size_t i = 0; i < g_stage.size(); i++) {
+            Staging& st = g_stage[i];
+            if (!st.taken && st.cap >= total && hipEventQuery(st.done) == hipSuccess) {
+                st.taken = true;
+                idx = (int)i;
+                break;
+            }
+        }
+        if (idx < 0) {
+            Staging st;
+            st.cap = std::max<size_t>(total, 1 << 16);
+            if (hipHostMalloc(&st.host, st.cap, hipHostMallocDefault) != hipSuccess)
+                return fail(ESQ_ENOMEM, "hipHostMalloc(staging)");
+            if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+                (void)hipHostFree(st.host);
+                return fail(ESQ_EHIP, "hipEventCreate(staging)");
+            }
+            st.taken = true;
+            g_stage.push_back(st);
+            idx = (int)g_stage.size() - 1;
+        }
+    }
+    Staging st;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        st = g_stage[idx];
+    }
+    size_t off = 0;
+    int rc = ESQ_OK;
+    for (size_t i = 0; i < parts.size(); i++) {
+        std::memcpy((char*)st.host + off, parts[i].first, parts[i].second);
+        hipError_t e = hipMemcpyAsync(dsts[i], (char*)st.host + off, parts[i].second,
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hipMemcpyAsync(descriptors)");
+            break;
+        }
+        off += (parts[i].second + 255) & ~(size_t)255;
+    }
+    (void)hipEventRecord(st.done, s);
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g_stage[idx].taken = false;
+    return rc;
+}
+
 uint64_t isqrt_u64(uint64_t x)
 {
     uint64_t r = (uint64_t)std::sqrt((double)x);
-    while (r * r > x)
+    while (r > 0 && r * r > x)
         r--;
     while ((r + 1) * (r + 1) <= x)
         r++;
@@ -135,9 +207,12 @@ void free_ctx(Ctx* c)
         return;
     if (c->device >= 0)
         (void)hipSetDevice(c->device);
-    for (auto& kv : c->med)
-        if (kv.second.d)
-            (void)hipFree(kv.second.d);
+    for (auto& kv : c->med) {
+        if (kv.second.tasks)
+            (void)hipFree(kv.second.tasks);
+        if (kv.second.medq)
+            (void)hipFree(kv.second.medq);
+    }
     if (c->d_primes)
         (void)hipFree(c->d_primes);
     if (c->d_wheel)
@@ -154,103 +229,72 @@ uint32_t prime_upper(const Ctx* c, uint64_t x)
                       c->primes.begin());
 }
 
-// Lane-tasks for the medium primes of a region of rw words: prime i (13 is
-// i = 0) with up to h = ceil(R / q) marks per region is split into
-// c = ceil(h / entry_hits) tasks; task v marks f + (v + c t) q, t >= 0.
-int get_med_table(Ctx* c, uint32_t rw, uint32_t nmed, uint32_t entry_hits, MedTable** out)
+// Medium primes primes[4 .. med_end) for a region of rw words and segment
+// length S: per prime (q, S mod q), and lane-tasks -- prime i with up to
+// h = ceil(R / q) marks per region is split into c = ceil(h / entry_hits)
+// tasks; task v marks f + (v + c t) q, t >= 0.
+int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_t entry_hits,
+                  MedTable** out)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    const auto key = std::make_tuple(rw, nmed, entry_hits);
+    const auto key = std::make_tuple(rw, log2S, med_end, entry_hits);
     auto it = c->med.find(key);
     if (it != c->med.end()) {
         *out = &it->second;
         return ESQ_OK;
     }
     const uint64_t R = (uint64_t)rw * 64;
-    std::vector<std::pair<uint64_t, MedEntry>> tasks;
+    const uint64_t S = 1ull << log2S;
+    const uint32_t nmed = med_end - 4;
+    std::vector<std::pair<uint64_t, MedTask>> tasks;
+    std::vector<uint2> medq(std::max<uint32_t>(nmed, 1));
     for (uint32_t i = 0; i < nmed; i++) {
         const uint64_t p = c->primes[4 + i];
         const uint64_t q = p * p;
+        medq[i].x = (uint32_t)q;
+        medq[i].y = (uint32_t)(S % q);
         const uint64_t h = (R + q - 1) / q;
         uint64_t parts = std::max<uint64_t>(1, (h + entry_hits - 1) / entry_hits);
         parts = std::min<uint64_t>(parts, 65535);
         for (uint64_t v = 0; v < parts; v++) {
-            MedEntry e;
-            e.idx = i;
-            e.vc = (uint32_t)v | ((uint32_t)parts << 16);
-            tasks.push_back({(h + parts - 1) / parts, e});
+            MedTask t;
+            t.q = (uint32_t)q;
+            t.idx = i;
+            t.vc = (uint32_t)v | ((uint32_t)parts << 16);
+            t.pad = 0;
+            tasks.push_back({(h + parts - 1) / parts, t});
         }
     }
     // lanes of one wave get tasks of similar length
     std::stable_sort(tasks.begin(), tasks.end(),
                      [](const auto& a, const auto& b) { return a.first > b.first; });
-    std::vector<MedEntry> host(tasks.size());
+    std::vector<MedTask> host(tasks.size());
     for (size_t i = 0; i < tasks.size(); i++)
         host[i] = tasks[i].second;
     MedTable t;
-    t.n = (uint32_t)host.size();
-    if (t.n) {
-        hipError_t e = hipMalloc(&t.d, host.size() * sizeof(MedEntry));
-        if (e != hipSuccess)
-            return hip_fail(e, "hipMalloc(medium table)");
-        e = hipMemcpy(t.d, host.data(), host.size() * sizeof(MedEntry), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(t.d);
-            return hip_fail(e, "hipMemcpy(medium table)");
+    t.n_tasks = (uint32_t)host.size();
+    hipError_t e = hipMalloc(&t.medq, medq.size() * sizeof(uint2));
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMalloc(medium primes)");
+    if ((e = hipMemcpy(t.medq, medq.data(), medq.size() * sizeof(uint2), hipMemcpyHostToDevice)) !=
+        hipSuccess) {
+        (void)hipFree(t.medq);
+        return hip_fail(e, "hipMemcpy(medium primes)");
+    }
+    if (t.n_tasks) {
+        if ((e = hipMalloc(&t.tasks, host.size() * sizeof(MedTask))) != hipSuccess) {
+            (void)hipFree(t.medq);
+            return hip_fail(e, "hipMalloc(medium tasks)");
+        }
+        if ((e = hipMemcpy(t.tasks, host.data(), host.size() * sizeof(MedTask),
+                           hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(t.medq);
+            (void)hipFree(t.tasks);
+            return hip_fail(e, "hipMemcpy(medium tasks)");
         }
     }
     auto res = c->med.emplace(key, t);
     *out = &res.first->second;
-    return ESQ_OK;
-}
-
-// Geometry of one call, shared by both entry points.
-struct Plan {
-    uint32_t S = 0, log2S = 0, hlo_words = 0, hup_words = 0, rw = 0, nseg = 0;
-    int64_t A0 = 0;
-    uint32_t med_end = 4, nmed = 0, b_begin = 0, b_end = 0, n_heavy = 0;
-    uint64_t E = 0, capacity = 0;
-};
-
-int make_plan(const Ctx* c, const Params& par, int64_t A0, uint64_t span_words,
-              uint32_t hlo_words, uint32_t hup_words, uint64_t pmax, Plan* pl)
-{
-    Plan p;
-    p.log2S = (uint32_t)par.seg_log2;
-    p.S = 1u << p.log2S;
-    p.hlo_words = hlo_words;
-    p.hup_words = hup_words;
-    p.rw = hlo_words + p.S / 64 + hup_words;
-    p.A0 = A0;
-    const uint64_t nseg = (span_words + p.S / 64 - 1) / (p.S / 64);
-    if (nseg > 0x7fffffffull)
-        return fail(ESQ_ERANGE, "too many segments");
-    p.nseg = (uint32_t)nseg;
-    if (pmax > c->plimit)
-        return fail(ESQ_ERANGE, "range exceeds the prime table built by esq_init");
-    const uint64_t R = (uint64_t)p.rw * 64;
-    const uint32_t pmax_end = prime_upper(c, pmax);
-    uint32_t med_end = std::min(prime_upper(c, isqrt_u64(R)), pmax_end);
-    med_end = std::max<uint32_t>(med_end, 4);
-    p.med_end = med_end;
-    p.nmed = std::min<uint32_t>(med_end - 4, (uint32_t)kMaxMedium);
-    p.med_end = 4 + p.nmed;
-    p.b_begin = p.med_end;
-    p.b_end = std::max(pmax_end, p.b_begin);
-    p.E = (uint64_t)(p.nseg - (p.nseg ? 1 : 0)) * p.S + R;
-    if (p.b_end > p.b_begin) {
-        const uint32_t heavy_end = prime_upper(c, isqrt_u64(p.E / 64));
-        p.n_heavy = heavy_end > p.b_begin ? std::min(heavy_end, p.b_end) - p.b_begin : 0;
-        const double sum_inv = c->inv_pref[p.b_end] - c->inv_pref[p.b_begin];
-        const double hits = std::ceil((double)p.E * sum_inv * (1.0 + 1e-9)) + (double)(p.b_end - p.b_begin);
-        // a hit lies in up to ceil(R / S) overlapping segment regions
-        const double dup = std::ceil((double)R / (double)p.S);
-        const double cap = dup * hits + 1024.0;
-        if (cap >= 4294967295.0)
-            return fail(ESQ_ERANGE, "range too long for one call (large-prime hit lists)");
-        p.capacity = (uint64_t)cap;
-    }
-    *pl = p;
     return ESQ_OK;
 }
 
@@ -265,109 +309,6 @@ uint32_t wheel_base(int64_t region_start)
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct Scratch {
-    char* base = nullptr;
-    Acc* acc = nullptr;
-    uint32_t *counts = nullptr, *cursor = nullptr, *offsets = nullptr, *entries = nullptr;
-    unsigned long long* tail_n = nullptr;
-    uint8_t* tail_d = nullptr;
-};
-
-int alloc_scratch(const Plan& p, uint64_t tail_cap, hipStream_t s, Scratch* sc)
-{
-    const bool buckets = p.b_end > p.b_begin;
-    size_t off = 0;
-    const size_t o_acc = off;
-    off = align_up(off + sizeof(Acc));
-    const size_t o_counts = off;
-    off = align_up(off + (buckets ? (size_t)p.nseg * 4 : 0));
-    const size_t o_cursor = off;
-    off = align_up(off + (buckets ? (size_t)p.nseg * 4 : 0));
-    const size_t o_offsets = off;
-    off = align_up(off + (buckets ? (size_t)(p.nseg + 1) * 4 : 0));
-    const size_t o_entries = off;
-    off = align_up(off + (buckets ? (size_t)p.capacity * 4 : 0));
-    const size_t o_tail_n = off;
-    off = align_up(off + (size_t)tail_cap * 8);
-    const size_t o_tail_d = off;
-    off = align_up(off + (size_t)tail_cap);
-    void* b = nullptr;
-    hipError_t e = hipMallocAsync(&b, off, s);
-    if (e != hipSuccess || !b)
-        return fail(ESQ_ENOMEM, std::string("hipMallocAsync(scratch): ") + hipGetErrorString(e));
-    sc->base = (char*)b;
-    sc->acc = (Acc*)(sc->base + o_acc);
-    if (buckets) {
-        sc->counts = (uint32_t*)(sc->base + o_counts);
-        sc->cursor = (uint32_t*)(sc->base + o_cursor);
-        sc->offsets = (uint32_t*)(sc->base + o_offsets);
-        sc->entries = (uint32_t*)(sc->base + o_entries);
-    }
-    sc->tail_n = (unsigned long long*)(sc->base + o_tail_n);
-    sc->tail_d = (uint8_t*)(sc->base + o_tail_d);
-    return ESQ_OK;
-}
-
-// Prepare + large-prime hit lists; shared by both entry points.
-int enqueue_sieve_setup(const Ctx* c, const Plan& p, const Scratch& sc, hipStream_t s)
-{
-    const bool buckets = p.b_end > p.b_begin;
-    hipError_t e = launch_prepare(sc.acc, buckets ? sc.counts : nullptr, sc.cursor, p.nseg, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "k_prepare");
-    if (!buckets || p.nseg == 0)
-        return ESQ_OK;
-    BucketParams bp;
-    std::memset(&bp, 0, sizeof(bp));
-    bp.primes = c->d_primes;
-    bp.p_begin = p.b_begin;
-    bp.n_heavy = p.n_heavy;
-    bp.n_light = p.b_end - p.b_begin - p.n_heavy;
-    bp.log2S = p.log2S;
-    bp.overlap = p.rw * 64 - p.S;
-    bp.nseg = p.nseg;
-    bp.B0 = p.A0 - (int64_t)p.hlo_words * 64;
-    bp.E = p.E;
-    bp.counts = sc.counts;
-    bp.cursor = sc.cursor;
-    bp.offsets = sc.offsets;
-    bp.entries = sc.entries;
-    bp.capacity = p.capacity;
-    bp.acc = sc.acc;
-    if ((e = launch_bucket(bp, false, s)) != hipSuccess)
-        return hip_fail(e, "k_bucket(count)");
-    if ((e = launch_scan(sc.counts, sc.offsets, p.nseg, sc.acc, p.capacity, s)) != hipSuccess)
-        return hip_fail(e, "k_scan");
-    if ((e = launch_bucket(bp, true, s)) != hipSuccess)
-        return hip_fail(e, "k_bucket(fill)");
-    return ESQ_OK;
-}
-
-void fill_seg_params(const Ctx* c, const Plan& p, const Scratch& sc, const MedTable* mt,
-                     SegParams* sp)
-{
-    std::memset(sp, 0, sizeof(*sp));
-    sp->A0 = p.A0;
-    sp->log2S = p.log2S;
-    sp->hlo_words = p.hlo_words;
-    sp->rw = p.rw;
-    sp->nseg = p.nseg;
-    sp->wheel_base0 = wheel_base(p.A0 - (int64_t)p.hlo_words * 64);
-    sp->wheel_step = (uint32_t)((p.S / 64) % kWheelPeriod);
-    sp->wheel = c->d_wheel;
-    sp->primes = c->d_primes;
-    sp->med_begin = 4;
-    sp->nmed = p.nmed;
-    sp->med = mt ? mt->d : nullptr;
-    sp->n_med_entries = mt ? mt->n : 0;
-    if (p.b_end > p.b_begin) {
-        sp->bucket_off = sc.offsets;
-        sp->bucket_ent = sc.entries;
-        sp->bucket_cap = p.capacity;
-    }
-    sp->acc = sc.acc;
-}
-
 int snapshot(Ctx** c, Params* par)
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -381,7 +322,327 @@ int snapshot(Ctx** c, Params* par)
     return ESQ_OK;
 }
 
+// One interval to process, in odd-index terms: verify -> the n-indices
+// [I0, I1); sieve -> the m-indices of the output bits.
+struct Req {
+    uint64_t I0, I1;
+    uint8_t* out_mink;
+    uint64_t* out_bits;
+};
+
+// A launch planned on the host: geometry, descriptors, scratch layout.
+struct Planned {
+    Launch L;
+    int mode = 0;
+    std::vector<Interval> ivs;
+    std::vector<uint4> items;
+    uint32_t max_direct = 0, max_cof = 0, grid = 0, block = 256;
+    bool any_bucket = false;
+    uint64_t nseg_total = 0;
+    size_t bytes = 0, o_iv = 0, o_acc = 0, o_items = 0, o_bcnt = 0, o_bslot = 0, o_misc = 0;
+    size_t o_tn = 0, o_tiv = 0, o_td = 0;
+};
+
+// Plan one launch over `reqs` (mode 0/1 verify, 2 sieve).
+int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<Req>& reqs,
+         Planned* P)
+{
+    const uint32_t n_iv = (uint32_t)reqs.size();
+    const uint32_t log2S = (uint32_t)par.seg_log2;
+    const uint64_t S = 1ull << log2S;
+    const uint32_t SW = (uint32_t)(S / 64);
+    const uint32_t kmax_eff = kmax ? kmax : 63;
+    const uint32_t klds = std::min<uint32_t>(kmax_eff, (uint32_t)par.kh);
+    uint32_t hlo = 0, hup = 0;
+    if (mode == 2) {
+        hup = 1;
+    } else {
+        hlo = (klds >= 7 ? (1u << (klds - 1)) : 64u) / 64;
+    }
+    const uint32_t rw = hlo + SW + hup;
+    const uint64_t R = (uint64_t)rw * 64;
+
+    // per-interval geometry
+    std::vector<Interval>& ivs = P->ivs;
+    ivs.assign(n_iv, Interval());
+    uint64_t nseg_total = 0, pmax_all = 0;
+    std::vector<uint64_t> pmax(n_iv, 0);
+    for (uint32_t i = 0; i < n_iv; i++) {
+        const Req& r = reqs[i];
+        Interval& v = ivs[i];
+        std::memset(&v, 0, sizeof(v));
+        v.I0 = r.I0;
+        v.I1 = r.I1;
+        v.A0 = (int64_t)(r.I0 & ~63ull);
+        v.out_mink = r.out_mink;
+        v.out_bits = r.out_bits;
+        v.out_shift = (uint32_t)(r.I0 - (uint64_t)v.A0);
+        if (r.I1 <= r.I0)
+            continue;
+        uint64_t nseg;
+        if (mode == 2) {
+            const uint64_t n_out = (r.I1 - r.I0 + 63) / 64;
+            nseg = (n_out + SW - 1) / SW;
+            pmax[i] = isqrt_u64(2 * (r.I1 - 1) + 1);                // last odd m
+        } else {
+            nseg = (r.I1 - (uint64_t)v.A0 + S - 1) / S;
+            const uint64_t n_last = 2 * (r.I1 - 1) + 1;
+            pmax[i] = n_last >= 3 ? isqrt_u64(n_last - 2) : 0;       // largest candidate
+        }
+        if (pmax[i] > c->plimit)
+            return fail(ESQ_ERANGE, "range exceeds the prime table built by esq_init");
+        v.nseg = (uint32_t)nseg;
+        v.seg_base = (uint32_t)nseg_total;
+        nseg_total += nseg;
+        if (nseg_total > 0x7fffffffull)
+            return fail(ESQ_ERANGE, "too many segments in one call");
+        v.wheel_base0 = wheel_base(v.A0 - (int64_t)hlo * 64);
+        pmax_all = std::max(pmax_all, pmax[i]);
+    }
+
+    // medium primes: 13 .. min(medium_max, largest needed)
+    uint32_t med_end = std::max<uint32_t>(4, prime_upper(c, std::min<uint64_t>(
+                                                  (uint64_t)par.medium_max, pmax_all)));
+    med_end = std::min<uint32_t>(med_end, 4 + (uint32_t)kMaxMedium);
+    const uint32_t direct_end = prime_upper(c, kCofactorPrime);
+    uint32_t max_direct = 0, max_cof = 0;
+    bool any_bucket = false;
+    uint32_t pmax_end_all = med_end;
+    for (uint32_t i = 0; i < n_iv; i++) {
+        Interval& v = ivs[i];
+        if (!v.nseg)
+            continue;
+        v.pmax_end = std::max(prime_upper(c, pmax[i]), med_end);
+        pmax_end_all = std::max(pmax_end_all, v.pmax_end);
+        v.b_direct_end = std::max(med_end, std::min(v.pmax_end, direct_end));
+        if (v.pmax_end > v.b_direct_end) {
+            const int64_t B0 = v.A0 - (int64_t)hlo * 64;
+            const uint64_t E = (uint64_t)(v.nseg - 1) * S + R;
+            const uint64_t m_hi = 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1;
+            const uint64_t jmax = m_hi / (kCofactorPrime * kCofactorPrime);
+            v.n_cof = (uint32_t)((jmax + 1) / 2);
+        }
+        if (v.pmax_end > med_end)
+            any_bucket = true;
+        max_direct = std::max(max_direct, v.b_direct_end - med_end);
+        max_cof = std::max(max_cof, v.n_cof);
+    }
+
+    MedTable* mt = nullptr;
+    int rc;
+    if (med_end > 4 && (rc = get_med_table(c, rw, log2S, med_end, (uint32_t)par.entry_hits, &mt)))
+        return rc;
+
+    uint32_t cap = 0;
+    if (any_bucket) {
+        if (par.bucket_cap > 0) {
+            cap = (uint32_t)par.bucket_cap;
+        } else {
+            const double expect = (double)R * (c->inv_pref[pmax_end_all] - c->inv_pref[med_end]);
+            cap = (uint32_t)std::ceil(8.0 * expect + 32.0);
+            cap = (cap + 7) & ~7u;
+        }
+    }
+
+    // work items: runs of consecutive segments
+    const int occ = verify_occupancy((uint32_t)par.block, (size_t)rw * 8);
+    const uint64_t resident = (uint64_t)c->n_cu * (uint64_t)occ;
+    std::vector<uint4>& items = P->items;
+    items.clear();
+    uint32_t n_items = 0;
+    if (n_iv == 1) {
+        n_items = (uint32_t)std::min<uint64_t>(nseg_total, resident);
+    } else {
+        const uint64_t target = std::max<uint64_t>(1, resident * (uint64_t)par.items_per_wg);
+        const uint64_t run = std::max<uint64_t>(1, (nseg_total + target - 1) / target);
+        for (uint32_t i = 0; i < n_iv; i++)
+            for (uint64_t b = 0; b < ivs[i].nseg; b += run) {
+                uint4 x;
+                x.x = i;
+                x.y = (uint32_t)b;
+                x.z = (uint32_t)std::min<uint64_t>(run, ivs[i].nseg - b);
+                x.w = 0;
+                items.push_back(x);
+            }
+        n_items = (uint32_t)items.size();
+    }
+    const uint64_t tail_cap = mode == 2 ? 1 : std::max<uint64_t>(1, (uint64_t)par.tail_cap);
+
+    // scratch layout, one allocation
+    size_t off = 0;
+    P->o_iv = off;
+    off = align_up(off + sizeof(Interval) * std::max<uint32_t>(n_iv, 1));
+    P->o_acc = off;
+    off = align_up(off + sizeof(Acc) * std::max<uint32_t>(n_iv, 1));
+    P->o_items = off;
+    off = align_up(off + sizeof(uint4) * items.size());
+    P->o_bcnt = off;
+    off = align_up(off + (any_bucket ? nseg_total * 4 : 0));
+    P->o_bslot = off;
+    off = align_up(off + (any_bucket ? nseg_total * cap * 4 : 0));
+    P->o_misc = off;
+    off = align_up(off + 64);
+    P->o_tn = off;
+    off = align_up(off + tail_cap * 8);
+    P->o_tiv = off;
+    off = align_up(off + tail_cap * 4);
+    P->o_td = off;
+    off = align_up(off + tail_cap);
+    P->bytes = off;
+
+    Launch& L = P->L;
+    std::memset(&L, 0, sizeof(L));
+    L.log2S = log2S;
+    L.hlo_words = hlo;
+    L.hup_words = hup;
+    L.rw = rw;
+    L.n_iv = n_iv;
+    L.n_items = n_items;
+    L.mode = (uint32_t)mode;
+    L.med_end = med_end;
+    L.n_tasks = mt ? mt->n_tasks : 0;
+    L.k_lds = mode == 2 ? 0 : klds;
+    L.kmax_eff = kmax_eff;
+    L.bucket_cap = cap;
+    L.nprimes = (uint32_t)c->primes.size();
+    L.primes = c->d_primes;
+    L.medq = mt ? mt->medq : nullptr;
+    L.tasks = mt ? mt->tasks : nullptr;
+    L.wheel = c->d_wheel;
+    L.tail_cap = tail_cap;
+    P->mode = mode;
+    P->max_direct = max_direct;
+    P->max_cof = max_cof;
+    P->any_bucket = any_bucket;
+    P->nseg_total = nseg_total;
+    P->grid = (uint32_t)std::min<uint64_t>(n_items, resident);
+    P->block = (uint32_t)par.block;
+    return ESQ_OK;
+}
+
+// Point the launch at its scratch (device pointer `base`).
+void bind(Planned* P, char* base)
+{
+    Launch& L = P->L;
+    Acc* accs = (Acc*)(base + P->o_acc);
+    for (size_t i = 0; i < P->ivs.size(); i++)
+        P->ivs[i].acc = accs + i;
+    L.iv = (const Interval*)(base + P->o_iv);
+    L.items = P->items.empty() ? nullptr : (const uint4*)(base + P->o_items);
+    L.bucket_cnt = P->any_bucket ? (uint32_t*)(base + P->o_bcnt) : nullptr;
+    L.bucket_slot = P->any_bucket ? (uint32_t*)(base + P->o_bslot) : nullptr;
+    L.queue = (unsigned int*)(base + P->o_misc);
+    L.tail_count = (unsigned long long*)(base + P->o_misc + 8);
+    L.tail_n = (unsigned long long*)(base + P->o_tn);
+    L.tail_iv = (uint32_t*)(base + P->o_tiv);
+    L.tail_d = (uint8_t*)(base + P->o_td);
+}
+
+// The kernels of one launch, in stream order (no allocation, no copy): this
+// is what a hipGraph captures.  With iv_by_value the single interval's
+// descriptor travels as a kernel argument instead of being uploaded.
+int launch_seq(const Planned& P, bool iv_by_value, bool profile, void* out_summaries,
+               void* out_records, uint64_t* out_exceptions, uint64_t exc_cap, hipStream_t s)
+{
+    const Launch& L = P.L;
+    Acc* accs = P.ivs.empty() ? nullptr : P.ivs[0].acc;
+    hipError_t e;
+    int rc;
+    if ((e = launch_prepare(L, accs, iv_by_value ? &P.ivs[0] : nullptr, (uint32_t)P.nseg_total,
+                            s)) != hipSuccess)
+        return hip_fail(e, "k_prepare");
+    if (P.any_bucket && (e = launch_bucket(L, P.max_direct, P.max_cof, s)) != hipSuccess)
+        return hip_fail(e, "k_bucket");
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (profile && (rc = prof_begin(s, &ev)))
+        return rc;
+    e = launch_verify(L, P.grid, P.block, s);
+    if (profile)
+        prof_end(s, ev);
+    if (e != hipSuccess)
+        return hip_fail(e, "k_verify");
+    if (P.mode != 2) {
+        if ((e = launch_tail(L, s)) != hipSuccess)
+            return hip_fail(e, "k_tail");
+        if ((e = launch_finalize(L, out_summaries, out_records, out_exceptions, exc_cap, s)) !=
+            hipSuccess)
+            return hip_fail(e, "k_finalize");
+    }
+    return ESQ_OK;
+}
+
+// Plan, allocate in stream order, upload, enqueue, release in stream order.
+int enqueue(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<Req>& reqs,
+            void* out_summaries, void* out_records, uint64_t* out_exceptions, uint64_t exc_cap,
+            hipStream_t s)
+{
+    Planned P;
+    int rc = plan(c, par, mode, kmax, reqs, &P);
+    if (rc)
+        return rc;
+    char* base = nullptr;
+    hipError_t e = hipMallocAsync((void**)&base, P.bytes, s);
+    if (e != hipSuccess || !base)
+        return fail(ESQ_ENOMEM, std::string("hipMallocAsync(scratch): ") + hipGetErrorString(e));
+    bind(&P, base);
+    const bool by_value = P.ivs.size() == 1;
+    if (!by_value) {
+        std::vector<std::pair<const void*, size_t>> parts;
+        std::vector<char*> dsts;
+        parts.push_back({P.ivs.data(), sizeof(Interval) * P.ivs.size()});
+        dsts.push_back(base + P.o_iv);
+        if (!P.items.empty()) {
+            parts.push_back({P.items.data(), sizeof(uint4) * P.items.size()});
+            dsts.push_back(base + P.o_items);
+        }
+        if ((rc = stage_upload(parts, dsts, s))) {
+            (void)hipFreeAsync(base, s);
+            return rc;
+        }
+    }
+    rc = launch_seq(P, by_value, par.profile != 0, out_summaries, out_records, out_exceptions,
+                    exc_cap, s);
+    (void)hipFreeAsync(base, s);
+    return rc;
+}
+
+int make_batch_reqs(const Ctx* c, uint32_t count, const uint64_t* lo, const uint64_t* hi,
+                    uint8_t* const* d_out_mink, std::vector<Req>* reqs, bool* per_n)
+{
+    reqs->assign(count, Req());
+    *per_n = false;
+    for (uint32_t i = 0; i < count; i++) {
+        if (lo[i] > hi[i])
+            return fail(ESQ_EINVAL, "lo > hi in entry " + std::to_string(i));
+        if (hi[i] > c->max_hi)
+            return fail(ESQ_ERANGE, "hi above the max_hi given to esq_init in entry " + std::to_string(i));
+        const uint64_t n0 = std::max<uint64_t>(lo[i], 3) | 1;
+        const uint64_t n_odd = hi[i] > n0 ? (hi[i] - n0 + 1) / 2 : 0;
+        Req& r = (*reqs)[i];
+        r.I0 = (n0 - 1) / 2;
+        r.I1 = r.I0 + n_odd;
+        r.out_mink = d_out_mink ? d_out_mink[i] : nullptr;
+        r.out_bits = nullptr;
+        *per_n = *per_n || r.out_mink;
+    }
+    return ESQ_OK;
+}
+
 }  // namespace
+
+// A prepared batch: planned once, scratch and descriptors resident, launched
+// any number of times (directly or as a replayed hipGraph).
+struct esq_batch {
+    Planned P;
+    char* base = nullptr;
+    int device = 0;
+    bool profile = false;
+    void* out_summaries = nullptr;
+    void* out_records = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture = nullptr;  // private stream the kernel sequence is captured on
+};
 
 extern "C" {
 
@@ -405,6 +666,10 @@ int esq_init(int device, uint64_t max_hi)
         g_ctx = new Ctx();
         g_ctx->device = device;
         fresh = true;
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            ncu > 0)
+            g_ctx->n_cu = ncu;
         if ((e = configure_kernels()) != hipSuccess) {
             free_ctx(g_ctx);
             g_ctx = nullptr;
@@ -433,7 +698,8 @@ int esq_init(int device, uint64_t max_hi)
         e = hipMalloc(&d, std::max<size_t>(pr.size(), 1) * 4);
         if (e != hipSuccess)
             return fail(ESQ_ENOMEM, "hipMalloc(primes)");
-        if (!pr.empty() && (e = hipMemcpy(d, pr.data(), pr.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+        if (!pr.empty() &&
+            (e = hipMemcpy(d, pr.data(), pr.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) {
             (void)hipFree(d);
             return hip_fail(e, "hipMemcpy(primes)");
         }
@@ -469,44 +735,16 @@ int esq_sieve_segment(uint64_t lo, uint64_t hi, uint64_t* d_bits, void* stream)
     const uint64_t m0 = lo | 1;
     if (hi <= m0)
         return ESQ_OK;
-    const uint64_t n_bits = (hi - m0 + 1) / 2;
     if (!d_bits)
         return fail(ESQ_EINVAL, "d_bits is null");
-    hipStream_t s = (hipStream_t)stream;
+    const uint64_t n_bits = (hi - m0 + 1) / 2;
     const uint64_t I0 = (m0 - 1) / 2;
-    const int64_t A0 = (int64_t)(I0 & ~63ull);
-    const uint64_t n_out = (n_bits + 63) / 64;
-    const uint64_t m_last = m0 + 2 * (n_bits - 1);
-    Plan p;
-    if ((rc = make_plan(c, par, A0, n_out, 0, 1, isqrt_u64(m_last), &p)))
-        return rc;
-    MedTable* mt = nullptr;
-    if (p.nmed && (rc = get_med_table(c, p.rw, p.nmed, (uint32_t)par.entry_hits, &mt)))
-        return rc;
-    Scratch sc;
-    if ((rc = alloc_scratch(p, 1, s, &sc)))
-        return rc;
-    if ((rc = enqueue_sieve_setup(c, p, sc, s))) {
-        (void)hipFreeAsync(sc.base, s);
-        return rc;
-    }
-    SegParams sp;
-    fill_seg_params(c, p, sc, mt, &sp);
-    sp.out_bits = d_bits;
-    sp.n_bits = n_bits;
-    sp.out_shift = (uint32_t)(I0 - (uint64_t)A0);
-    std::pair<hipEvent_t, hipEvent_t> ev;
-    if (par.profile && (rc = prof_begin(s, &ev))) {
-        (void)hipFreeAsync(sc.base, s);
-        return rc;
-    }
-    hipError_t e = launch_segment(sp, 2, (uint32_t)par.block, s);
-    if (par.profile)
-        prof_end(s, ev);
-    (void)hipFreeAsync(sc.base, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "k_segment(sieve)");
-    return ESQ_OK;
+    std::vector<Req> reqs(1);
+    reqs[0].I0 = I0;
+    reqs[0].I1 = I0 + n_bits;
+    reqs[0].out_mink = nullptr;
+    reqs[0].out_bits = d_bits;
+    return enqueue(c, par, 2, 0, reqs, nullptr, nullptr, nullptr, 0, (hipStream_t)stream);
 }
 
 int esq_verify_range(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t* d_out_mink,
@@ -531,94 +769,146 @@ int esq_verify_range(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t* d_out_min
         return fail(ESQ_EINVAL, "out_exceptions is null but exceptions_cap > 0");
     if (hi > c->max_hi)
         return fail(ESQ_ERANGE, "hi above the max_hi given to esq_init");
-    hipStream_t s = (hipStream_t)stream;
     const uint64_t n0 = std::max<uint64_t>(lo, 3) | 1;
     const uint64_t n_odd = hi > n0 ? (hi - n0 + 1) / 2 : 0;
-    const uint32_t kmax_eff = kmax ? kmax : 63;
-    const uint32_t klds = std::min<uint32_t>(kmax_eff, (uint32_t)par.kh);
-    const uint32_t hbits = klds >= 7 ? (1u << (klds - 1)) : 64u;
-    const uint64_t I0 = (n0 - 1) / 2, I1 = I0 + n_odd;
-    const int64_t A0 = (int64_t)(I0 & ~63ull);
-    Plan p;
-    if (n_odd) {
-        const uint64_t span = (I1 - (uint64_t)A0 + 63) / 64;
-        const uint64_t n_last = n0 + 2 * (n_odd - 1);
-        if ((rc = make_plan(c, par, A0, span, hbits / 64, 0, isqrt_u64(n_last - 2), &p)))
-            return rc;
-    }
-    MedTable* mt = nullptr;
-    if (n_odd && p.nmed && (rc = get_med_table(c, p.rw, p.nmed, (uint32_t)par.entry_hits, &mt)))
+    std::vector<Req> reqs(1);
+    reqs[0].I0 = (n0 - 1) / 2;
+    reqs[0].I1 = reqs[0].I0 + n_odd;
+    reqs[0].out_mink = d_out_mink;
+    reqs[0].out_bits = nullptr;
+    return enqueue(c, par, d_out_mink ? 1 : 0, kmax, reqs, out_summary, out_records,
+                   exceptions_cap ? out_exceptions : nullptr, exceptions_cap, (hipStream_t)stream);
+}
+
+int esq_verify_batch(uint32_t count, const uint64_t* lo, const uint64_t* hi, uint32_t kmax,
+                     uint8_t* const* d_out_mink, esq_summary* out_summaries,
+                     esq_record* out_records, void* stream)
+{
+    t_err.clear();
+    Ctx* c;
+    Params par;
+    int rc = snapshot(&c, &par);
+    if (rc)
         return rc;
-    const uint64_t tail_cap = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)par.tail_cap, n_odd));
-    Scratch sc;
-    if ((rc = alloc_scratch(p, tail_cap, s, &sc)))
+    if (count == 0)
+        return ESQ_OK;
+    if (!lo || !hi || !out_summaries)
+        return fail(ESQ_EINVAL, "null lo, hi or out_summaries");
+    if (kmax > 63)
+        return fail(ESQ_EINVAL, "kmax > 63");
+    std::vector<Req> reqs;
+    bool per_n = false;
+    if ((rc = make_batch_reqs(c, count, lo, hi, d_out_mink, &reqs, &per_n)))
         return rc;
-    hipError_t e;
-    if (n_odd) {
-        if ((rc = enqueue_sieve_setup(c, p, sc, s))) {
-            (void)hipFreeAsync(sc.base, s);
-            return rc;
-        }
-        SegParams sp;
-        fill_seg_params(c, p, sc, mt, &sp);
-        sp.I0 = I0;
-        sp.I1 = I1;
-        sp.k_lds = klds;
-        sp.tail_n = sc.tail_n;
-        sp.tail_cap = tail_cap;
-        sp.out_mink = d_out_mink;
-        std::pair<hipEvent_t, hipEvent_t> ev;
-        if (par.profile && (rc = prof_begin(s, &ev))) {
-            (void)hipFreeAsync(sc.base, s);
-            return rc;
-        }
-        e = launch_segment(sp, d_out_mink ? 1 : 0, (uint32_t)par.block, s);
-        if (par.profile)
-            prof_end(s, ev);
-        if (e != hipSuccess) {
-            (void)hipFreeAsync(sc.base, s);
-            return hip_fail(e, "k_segment");
-        }
-        TailParams tp;
-        std::memset(&tp, 0, sizeof(tp));
-        tp.acc = sc.acc;
-        tp.tail_n = sc.tail_n;
-        tp.tail_d = sc.tail_d;
-        tp.tail_cap = tail_cap;
-        tp.primes = c->d_primes;
-        tp.nprimes = (uint32_t)c->primes.size();
-        tp.k_lds = klds;
-        tp.kmax_eff = kmax_eff;
-        tp.I0 = I0;
-        tp.out_mink = d_out_mink;
-        if ((e = launch_tail(tp, s)) != hipSuccess) {
-            (void)hipFreeAsync(sc.base, s);
-            return hip_fail(e, "k_tail");
-        }
-    } else {
-        if ((e = launch_prepare(sc.acc, nullptr, nullptr, 0, s)) != hipSuccess) {
-            (void)hipFreeAsync(sc.base, s);
-            return hip_fail(e, "k_prepare");
-        }
+    return enqueue(c, par, per_n ? 1 : 0, kmax, reqs, out_summaries, out_records, nullptr, 0,
+                   (hipStream_t)stream);
+}
+
+int esq_batch_create(uint32_t count, const uint64_t* lo, const uint64_t* hi, uint32_t kmax,
+                     uint8_t* const* d_out_mink, esq_summary* out_summaries,
+                     esq_record* out_records, esq_batch** out_handle)
+{
+    t_err.clear();
+    if (!out_handle)
+        return fail(ESQ_EINVAL, "out_handle is null");
+    *out_handle = nullptr;
+    Ctx* c;
+    Params par;
+    int rc = snapshot(&c, &par);
+    if (rc)
+        return rc;
+    if (count == 0 || !lo || !hi || !out_summaries)
+        return fail(ESQ_EINVAL, "empty batch or null lo, hi, out_summaries");
+    if (kmax > 63)
+        return fail(ESQ_EINVAL, "kmax > 63");
+    std::vector<Req> reqs;
+    bool per_n = false;
+    if ((rc = make_batch_reqs(c, count, lo, hi, d_out_mink, &reqs, &per_n)))
+        return rc;
+    esq_batch* b = new esq_batch();
+    b->device = c->device;
+    b->profile = par.profile != 0;
+    b->out_summaries = out_summaries;
+    b->out_records = out_records;
+    if ((rc = plan(c, par, per_n ? 1 : 0, kmax, reqs, &b->P))) {
+        delete b;
+        return rc;
     }
-    FinParams fp;
-    std::memset(&fp, 0, sizeof(fp));
-    fp.acc = sc.acc;
-    fp.tail_n = sc.tail_n;
-    fp.tail_d = sc.tail_d;
-    fp.tail_cap = tail_cap;
-    fp.n_odd = n_odd;
-    fp.I0 = I0;
-    fp.k_lds = n_odd ? klds : 0;
-    fp.out_summary = out_summary;
-    fp.out_records = out_records;
-    fp.out_exceptions = out_exceptions;
-    fp.exc_cap = exceptions_cap;
-    e = launch_finalize(fp, s);
-    (void)hipFreeAsync(sc.base, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "k_finalize");
+    hipError_t e = hipMalloc((void**)&b->base, b->P.bytes);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(ESQ_ENOMEM, "hipMalloc(batch scratch)");
+    }
+    bind(&b->P, b->base);
+    if ((e = hipMemcpy(b->base + b->P.o_iv, b->P.ivs.data(), sizeof(Interval) * b->P.ivs.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (!b->P.items.empty() &&
+         (e = hipMemcpy(b->base + b->P.o_items, b->P.items.data(),
+                        sizeof(uint4) * b->P.items.size(), hipMemcpyHostToDevice)) != hipSuccess)) {
+        (void)hipFree(b->base);
+        delete b;
+        return hip_fail(e, "hipMemcpy(batch descriptors)");
+    }
+    *out_handle = b;
     return ESQ_OK;
+}
+
+int esq_batch_launch(esq_batch* b, int use_graph, void* stream)
+{
+    t_err.clear();
+    if (!b)
+        return fail(ESQ_EINVAL, "null batch");
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if (!use_graph)
+        return launch_seq(b->P, false, b->profile, b->out_summaries, b->out_records, nullptr, 0, s);
+    if (!b->exec) {
+        // capture on a private stream (the legacy default stream cannot be
+        // captured); the instantiated graph is launched on the caller's stream
+        if (!b->capture &&
+            (e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreate(capture)");
+        if ((e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        int rc = launch_seq(b->P, false, false, b->out_summaries, b->out_records, nullptr, 0,
+                            b->capture);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->capture, &g);
+        if (rc) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamEndCapture");
+        if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        b->graph = g;
+    }
+    if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess)
+        return hip_fail(e, "hipGraphLaunch");
+    return ESQ_OK;
+}
+
+void esq_batch_destroy(esq_batch* b)
+{
+    if (!b)
+        return;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    if (b->capture)
+        (void)hipStreamDestroy(b->capture);
+    if (b->base)
+        (void)hipFree(b->base);
+    delete b;
 }
 
 int esq_set_param(const char* name, int64_t value)
@@ -644,14 +934,26 @@ int esq_set_param(const char* name, int64_t value)
         if (value < 1 || value > 4096)
             return fail(ESQ_EINVAL, "entry_hits out of range");
         g_par.entry_hits = (int)value;
-    } else if (n == "profile") {
-        if (value < 0 || value > 1)
-            return fail(ESQ_EINVAL, "profile must be 0 or 1");
-        g_par.profile = (int)value;
     } else if (n == "tail_cap") {
         if (value < 1 || value > (int64_t)1 << 30)
             return fail(ESQ_EINVAL, "tail_cap out of range");
         g_par.tail_cap = value;
+    } else if (n == "profile") {
+        if (value < 0 || value > 1)
+            return fail(ESQ_EINVAL, "profile must be 0 or 1");
+        g_par.profile = (int)value;
+    } else if (n == "medium_max") {
+        if (value < 11 || value > 11000)
+            return fail(ESQ_EINVAL, "medium_max out of range");
+        g_par.medium_max = value;
+    } else if (n == "bucket_cap") {
+        if (value < 0 || value > 4096)
+            return fail(ESQ_EINVAL, "bucket_cap out of range");
+        g_par.bucket_cap = value;
+    } else if (n == "items_per_wg") {
+        if (value < 1 || value > 1024)
+            return fail(ESQ_EINVAL, "items_per_wg out of range");
+        g_par.items_per_wg = value;
     } else {
         return fail(ESQ_EINVAL, "unknown parameter " + n);
     }
@@ -670,6 +972,9 @@ int64_t esq_get_param(const char* name)
     if (n == "entry_hits") return g_par.entry_hits;
     if (n == "tail_cap") return g_par.tail_cap;
     if (n == "profile") return g_par.profile;
+    if (n == "medium_max") return g_par.medium_max;
+    if (n == "bucket_cap") return g_par.bucket_cap;
+    if (n == "items_per_wg") return g_par.items_per_wg;
     return -1;
 }
 
@@ -712,6 +1017,12 @@ void esq_shutdown(void)
     }
     free_ctx(g_ctx);
     g_ctx = nullptr;
+    std::lock_guard<std::mutex> sl(g_stage_mu);
+    for (auto& st : g_stage) {
+        (void)hipHostFree(st.host);
+        (void)hipEventDestroy(st.done);
+    }
+    g_stage.clear();
 }
 
 }  // extern "C"

@@ -1,17 +1,20 @@
 // HIP kernels for gfx950 (wave64).  Exact integer work only: no floating
-// point and no matrix cores -- the sieve and the search are bit operations.
+// point on any result and no matrix cores -- the sieve and the search are bit
+// operations over 64-bit words.
 //
-//   k_wheel_build  periodic pattern of odd multiples of 9, 25, 49, 121
-//   k_prepare      zero the per-call accumulators
-//   k_bucket       large primes (p^2 above the LDS region): scatter every odd
-//                  multiple of p^2 into per-segment hit lists (count / fill)
-//   k_scan         exclusive scan of the per-segment hit counts
-//   k_segment      one workgroup per segment: Algorithm 1 in LDS, then
-//                  Algorithm 2 as a bit-sliced scan over the LDS bitmap
+//   k_wheel_build  periodic pattern of odd multiples of 9, 25, 49, 121 (once)
+//   k_prepare      zero the per-launch accumulators and the work queue
+//   k_bucket       primes above the medium range: every odd multiple of p^2
+//                  that falls in a segment region goes to that segment's hit
+//                  slots (by first hit for p <= 2^20, by cofactor above)
+//   k_verify       persistent workgroups pull runs of consecutive segments;
+//                  per segment: Algorithm 1 in LDS, then Algorithm 2 as a
+//                  bit-sliced scan of the LDS bitmap (or, in sieve mode, the
+//                  bitmap streamed to HBM)
 //   k_tail         exact search for the rare n not resolved from LDS
-//   k_finalize     aggregates, record-setters, sorted exceptions
-#include "esq_internal.h"
+//   k_finalize     per interval: aggregates, record-setters, exceptions
 #include "esq.h"
+#include "esq_internal.h"
 
 namespace esq {
 
@@ -43,31 +46,43 @@ hipError_t launch_wheel_build(uint64_t* wheel, hipStream_t s)
 
 // --------------------------------------------------------------- prepare
 
-__global__ void k_prepare(Acc* acc, uint32_t* counts, uint32_t* cursor, uint32_t nseg)
+__global__ void k_prepare(Launch L, Acc* accs, Interval iv0, int write_iv0, uint32_t nseg_total)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = t; i < 65; i += stride) {
-        acc->cnt[i] = 0;
-        acc->first[i] = kNone;
-        acc->deep_hist[i] = 0;
-    }
-    if (t == 0) {
-        acc->tail_count = 0;
-        acc->status = 0;
-        acc->bucket_total = 0;
-    }
-    if (counts)
-        for (uint32_t i = t; i < nseg; i += stride) {
-            counts[i] = 0;
-            cursor[i] = 0;
+    if (write_iv0 && t == 0)
+        *const_cast<Interval*>(L.iv) = iv0;
+    for (uint32_t i = t; i < L.n_iv * 65u; i += stride) {
+        Acc* a = accs + i / 65u;
+        const uint32_t k = i % 65u;
+        if (k < 16)
+            a->cnt[k] = 0;
+        a->first[k] = kNone;
+        a->deep_hist[k] = 0;
+        if (k == 0) {
+            a->tail_count = 0;
+            a->status = 0;
+            a->pad = 0;
         }
+    }
+    if (L.bucket_cnt)
+        for (uint32_t i = t; i < nseg_total; i += stride)
+            L.bucket_cnt[i] = 0;
+    if (t == 0) {
+        *L.queue = 0;
+        *L.tail_count = 0;
+    }
 }
 
-hipError_t launch_prepare(Acc* acc, uint32_t* counts, uint32_t* cursor, uint32_t nseg,
-                          hipStream_t s)
+hipError_t launch_prepare(const Launch& L, Acc* accs, const Interval* iv_single,
+                          uint32_t nseg_total, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prepare, dim3(64), dim3(256), 0, s, acc, counts, cursor, nseg);
+    Interval iv0;
+    __builtin_memset(&iv0, 0, sizeof(iv0));
+    if (iv_single)
+        iv0 = *iv_single;
+    hipLaunchKernelGGL(k_prepare, dim3(256), dim3(256), 0, s, L, accs, iv0, iv_single ? 1 : 0,
+                       nseg_total);
     return hipGetLastError();
 }
 
@@ -83,111 +98,97 @@ __device__ __forceinline__ uint64_t first_hit(int64_t B0, uint64_t q)
     return (uint64_t)f;
 }
 
-template <bool FILL>
-__device__ __forceinline__ void bucket_put(const BucketParams& p, uint32_t seg, uint32_t off)
+__device__ __forceinline__ uint64_t isqrt_floor(uint64_t x)
 {
-    if (!FILL) {
-        atomicAdd(&p.counts[seg], 1u);
-    } else {
-        const uint32_t pos = atomicAdd(&p.cursor[seg], 1u);
-        const uint64_t idx = (uint64_t)p.offsets[seg] + pos;
-        if (idx < p.capacity)
-            p.entries[idx] = off;
-        else
-            atomicOr(&p.acc->status, (unsigned)ESQ_STATUS_BUCKET_OVERFLOW);
-    }
+    uint64_t r = (uint64_t)sqrt((double)x);
+    while (r > 0 && r * r > x)
+        r--;
+    while ((r + 1) * (r + 1) <= x)
+        r++;
+    return r;
 }
 
-// Segment s covers y in [s S, s S + S + overlap): a hit belongs to segment
-// floor(y / S) and to every earlier segment whose region still reaches it.
-template <bool FILL>
-__device__ __forceinline__ void bucket_emit(const BucketParams& p, uint64_t y)
+// Segment s of an interval covers region offsets y in [s S, s S + R): a hit
+// belongs to segment floor(y / S) and to each earlier segment still reaching it.
+__device__ __forceinline__ void bucket_emit(const Launch& L, const Interval& iv, uint64_t y)
 {
-    uint64_t seg = y >> p.log2S;
-    uint64_t off = y & ((1ull << p.log2S) - 1);
-    const uint64_t R = (1ull << p.log2S) + p.overlap;
+    const uint64_t S = 1ull << L.log2S;
+    const uint64_t R = (uint64_t)L.rw * 64;
+    uint64_t seg = y >> L.log2S;
+    uint64_t off = y & (S - 1);
     while (off < R) {
-        if (seg < p.nseg)
-            bucket_put<FILL>(p, (uint32_t)seg, (uint32_t)off);
+        if (seg < iv.nseg) {
+            const uint32_t gs = iv.seg_base + (uint32_t)seg;
+            const uint32_t pos = atomicAdd(&L.bucket_cnt[gs], 1u);
+            if (pos < L.bucket_cap)
+                L.bucket_slot[(uint64_t)gs * L.bucket_cap + pos] = (uint32_t)off;
+        }
         if (seg == 0)
             break;
         seg--;
-        off += 1ull << p.log2S;
+        off += S;
     }
 }
 
-template <bool FILL>
-__global__ __launch_bounds__(256) void k_bucket(BucketParams p)
+// grid.y = interval; threads [0, max_direct) take the bucket primes up to
+// kCofactorPrime one each, the following threads one odd cofactor j each.
+__global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t max_direct)
 {
-    if (blockIdx.x < p.n_heavy) {
-        // a prime with many hits: the workgroup strides over them
-        const uint64_t pr = p.primes[p.p_begin + blockIdx.x];
-        const uint64_t q = pr * pr;
-        const uint64_t f = first_hit(p.B0, q);
-        if (f >= p.E)
+    const Interval iv = L.iv[blockIdx.y];
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t B0 = iv.A0 - (int64_t)L.hlo_words * 64;
+    const uint64_t S = 1ull << L.log2S;
+    const uint64_t E = (uint64_t)(iv.nseg ? iv.nseg - 1 : 0) * S + (uint64_t)L.rw * 64;
+    if (iv.nseg == 0)
+        return;
+    if (t < max_direct) {
+        const uint64_t pi = L.med_end + t;
+        if (pi >= iv.b_direct_end)
             return;
-        const uint64_t nh = (p.E - 1 - f) / q + 1;
-        for (uint64_t t = threadIdx.x; t < nh; t += blockDim.x)
-            bucket_emit<FILL>(p, f + t * q);
-    } else {
-        const uint64_t i = (uint64_t)(blockIdx.x - p.n_heavy) * blockDim.x + threadIdx.x;
-        if (i >= p.n_light)
-            return;
-        const uint64_t pr = p.primes[p.p_begin + p.n_heavy + i];
-        const uint64_t q = pr * pr;
-        for (uint64_t y = first_hit(p.B0, q); y < p.E; y += q)
-            bucket_emit<FILL>(p, y);
+        const uint64_t p = L.primes[pi];
+        const uint64_t q = p * p;
+        for (uint64_t y = first_hit(B0, q); y < E; y += q)
+            bucket_emit(L, iv, y);
+        return;
+    }
+    const uint64_t c = t - max_direct;
+    if (c >= iv.n_cof || iv.b_direct_end >= iv.pmax_end)
+        return;
+    // odd multiples j p^2 of the primes above kCofactorPrime, for one odd j
+    const uint64_t j = 2 * c + 1;
+    const uint64_t m_lo = B0 > 0 ? 2 * (uint64_t)B0 + 1 : 1;
+    const uint64_t m_hi = 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1;
+    uint64_t pa = isqrt_floor((m_lo + j - 1) / j);
+    if (pa * pa * j < m_lo)
+        pa++;
+    const uint64_t pb = isqrt_floor(m_hi / j);
+    // first prime >= pa among primes[b_direct_end, pmax_end)
+    uint32_t lo = iv.b_direct_end, hi = iv.pmax_end;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if ((uint64_t)L.primes[mid] < pa)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    for (uint32_t i = lo; i < iv.pmax_end; i++) {
+        const uint64_t p = L.primes[i];
+        if (p > pb)
+            break;
+        const uint64_t m = j * p * p;
+        if (m < m_lo || m > m_hi)
+            continue;
+        bucket_emit(L, iv, (m - 1) / 2 - (uint64_t)B0);
     }
 }
 
-hipError_t launch_bucket(const BucketParams& p, bool fill, hipStream_t s)
+hipError_t launch_bucket(const Launch& L, uint32_t max_direct, uint32_t max_cof, hipStream_t s)
 {
-    const uint32_t blocks = p.n_heavy + (p.n_light + 255) / 256;
-    if (blocks == 0)
+    const uint64_t threads = (uint64_t)max_direct + max_cof;
+    if (threads == 0 || L.n_iv == 0)
         return hipSuccess;
-    if (fill)
-        hipLaunchKernelGGL(k_bucket<true>, dim3(blocks), dim3(256), 0, s, p);
-    else
-        hipLaunchKernelGGL(k_bucket<false>, dim3(blocks), dim3(256), 0, s, p);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(1024) void k_scan(const uint32_t* counts, uint32_t* offsets,
-                                               uint32_t nseg, Acc* acc, uint64_t capacity)
-{
-    __shared__ unsigned long long part[1024];
-    const uint32_t T = blockDim.x, t = threadIdx.x;
-    const uint32_t per = (nseg + T - 1) / T;
-    const uint32_t b = min(t * per, nseg), e = min(b + per, nseg);
-    unsigned long long sum = 0;
-    for (uint32_t i = b; i < e; i++)
-        sum += counts[i];
-    part[t] = sum;
-    __syncthreads();
-    for (uint32_t off = 1; off < T; off <<= 1) {
-        const unsigned long long v = t >= off ? part[t - off] : 0ull;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    unsigned long long run = part[t] - sum;
-    for (uint32_t i = b; i < e; i++) {
-        offsets[i] = (uint32_t)run;
-        run += counts[i];
-    }
-    if (t == T - 1) {
-        const unsigned long long tot = part[T - 1];
-        offsets[nseg] = (uint32_t)tot;
-        acc->bucket_total = (unsigned)(tot > 0xffffffffull ? 0xffffffffull : tot);
-        if (tot > capacity)
-            atomicOr(&acc->status, (unsigned)ESQ_STATUS_BUCKET_OVERFLOW);
-    }
-}
-
-hipError_t launch_scan(const uint32_t* counts, uint32_t* offsets, uint32_t nseg, Acc* acc,
-                       uint64_t capacity, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, offsets, nseg, acc, capacity);
+    const uint32_t bx = (uint32_t)((threads + 255) / 256);
+    hipLaunchKernelGGL(k_bucket, dim3(bx, L.n_iv), dim3(256), 0, s, L, max_direct);
     return hipGetLastError();
 }
 
@@ -242,225 +243,324 @@ __device__ __forceinline__ void store_depths(uint8_t* out, const uint32_t (&D)[1
     }
 }
 
+__device__ __forceinline__ void mark(uint32_t* bm32, uint32_t pos)
+{
+    atomicOr(&bm32[pos >> 5], 1u << (pos & 31));
+}
+
 // MODE 0: verify, aggregates only; MODE 1: verify + per-n bytes;
 // MODE 2: Algorithm 1 alone, bitmap to HBM.
 template <int MODE>
-__global__ __launch_bounds__(1024) void k_segment(SegParams P)
+__global__ __launch_bounds__(1024) void k_verify(Launch L)
 {
     extern __shared__ uint64_t bm[];
     __shared__ uint32_t s_f[kMaxMedium];
-    __shared__ uint32_t s_q[kMaxMedium];
-    __shared__ uint32_t s_cnt[kMaxKh + 2];
-    __shared__ uint32_t s_first[kMaxKh + 2];
+    __shared__ unsigned long long s_first[kMaxKh + 2];
+    __shared__ uint32_t s_cnt[kMaxKh + 1];
+    __shared__ uint32_t s_item[4];
 
-    const uint32_t tid = threadIdx.x, T = blockDim.x, seg = blockIdx.x;
-    const uint32_t S = 1u << P.log2S;
-    const int64_t Bs = P.A0 - (int64_t)P.hlo_words * 64 + (int64_t)seg * (int64_t)S;
-    const int64_t gw0 = Bs / 64;  // exact: Bs is a multiple of 64
-    const uint32_t wb =
-        (uint32_t)(((uint64_t)P.wheel_base0 + (uint64_t)seg * P.wheel_step) % kWheelPeriod);
-
-    // 1. initialise: wheel pattern; words below odd index 0 are all "marked"
-    for (uint32_t w = tid; w < P.rw; w += T)
-        bm[w] = (gw0 + (int64_t)w < 0) ? ~0ull : P.wheel[wb + w];
-    // first hit of each medium prime inside the region
-    for (uint32_t i = tid; i < P.nmed; i += T) {
-        const uint32_t pr = P.primes[P.med_begin + i];
-        const uint32_t q = pr * pr;
-        const int64_t d = (int64_t)((q - 1) >> 1) - Bs;
-        int64_t f = d % (int64_t)q;
-        if (f < 0)
-            f += q;
-        s_f[i] = (uint32_t)f;
-        s_q[i] = q;
-    }
-    if (tid < kMaxKh + 2) {
-        s_cnt[tid] = 0;
-        s_first[tid] = kNone32;
-    }
-    __syncthreads();
-
-    // 2. mark odd multiples of p^2: medium primes by lane-tasks, large ones
-    //    from this segment's hit list
+    const uint32_t tid = threadIdx.x, T = blockDim.x, lane = tid & 63u;
+    const uint32_t S = 1u << L.log2S, SW = S >> 6;
+    const uint32_t R = L.rw * 64;
+    const uint32_t HW = L.hlo_words;
+    const uint32_t nmed = L.med_end - 4;
+    const uint32_t klds = L.k_lds;
+    const uint32_t wstep = SW % kWheelPeriod;
     uint32_t* bm32 = reinterpret_cast<uint32_t*>(bm);
-    const uint32_t R = P.rw * 64;
-    for (uint32_t e = tid; e < P.n_med_entries; e += T) {
-        const MedEntry me = P.med[e];
-        const uint32_t q = s_q[me.idx];
-        const uint32_t v = me.vc & 0xffffu, c = me.vc >> 16;
-        const uint64_t p0 = (uint64_t)s_f[me.idx] + (uint64_t)v * q;
-        if (p0 >= R)
-            continue;
-        const uint32_t step = c * q;
-        for (uint32_t pos = (uint32_t)p0; pos < R; pos += step)
-            atomicOr(&bm32[pos >> 5], 1u << (pos & 31));
-    }
-    if (P.bucket_off) {
-        const uint32_t b0 = P.bucket_off[seg];
-        const uint32_t b1 = (uint32_t)min((uint64_t)P.bucket_off[seg + 1], P.bucket_cap);
-        for (uint32_t e = b0 + tid; e < b1; e += T) {
-            const uint32_t pos = P.bucket_ent[e];
-            if (pos < R)
-                atomicOr(&bm32[pos >> 5], 1u << (pos & 31));
-        }
-    }
-    __syncthreads();
 
-    if (MODE == 2) {
-        // output word wo = seg * S/64 + lw covers odd indices I0 + 64 wo ...:
-        // region bits out_shift + 64 lw ... (words lw and lw + 1)
-        const uint32_t SW = S / 64;
-        const uint32_t sh = P.out_shift;
-        for (uint32_t lw = tid; lw < SW; lw += T) {
-            const uint64_t wo = (uint64_t)seg * SW + lw;
-            if (wo * 64 >= P.n_bits)
-                break;
-            const uint64_t lo = bm[lw], hi = bm[lw + 1];
-            const uint64_t v = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
-            uint64_t out = ~v;
-            const uint64_t rem = P.n_bits - wo * 64;
-            if (rem < 64)
-                out &= (1ull << rem) - 1;
-            P.out_bits[wo] = out;
-        }
-        return;
-    }
-
-    // 3. Algorithm 2, bit-sliced: U holds the n of one word still without a
-    //    representation; step k keeps n whose n - 2^k (2^(k-1) bits lower) is
-    //    marked.  cnt[k] counts U after step k; s_first[k+1] the first n in it.
-    const uint32_t HW = P.hlo_words;
-    const uint64_t As = (uint64_t)(P.A0 + (int64_t)seg * (int64_t)S);
-    const uint32_t lane = tid & 63u;
-    const uint32_t klds = P.k_lds;
-    uint32_t cnt[kMaxKh + 1];
-#pragma unroll
-    for (int k = 0; k <= kMaxKh; k++)
-        cnt[k] = 0;
-    uint32_t found = 0;
-
-    for (uint32_t w = HW + tid; w < P.rw; w += T) {
-        const uint64_t j0 = As + (uint64_t)(w - HW) * 64;
-        const uint64_t V = valid_mask(j0, P.I0, P.I1);
-        uint64_t U = V;
-        const uint64_t cur = bm[w], prv = bm[w - 1];
-        uint32_t D[16];
-        if (MODE == 1) {
-#pragma unroll
-            for (int i = 0; i < 16; i++)
-                D[i] = spread4((uint32_t)(V >> (4 * i)) & 15u);
-        }
-#pragma unroll
-        for (int k = 1; k <= kMaxKh; k++) {
-            if (k > (int)klds)
-                break;
-            uint64_t win;
-            if (k <= 6) {
-                const int sh = 1 << (k - 1);
-                win = (cur << sh) | (prv >> (64 - sh));
-            } else if (k == 7) {
-                win = prv;
-            } else {
-                win = U ? bm[w - (1u << (k - 7))] : 0ull;
-            }
-            U &= win;
-            cnt[k] += (uint32_t)__popcll(U);
-            if (MODE == 1) {
-#pragma unroll
-                for (int i = 0; i < 16; i++)
-                    D[i] += spread4((uint32_t)(U >> (4 * i)) & 15u);
-            }
-            const uint64_t b = __ballot(U != 0);
-            if (b == 0)
-                break;
-            if (!(found & (1u << (k + 1)))) {
-                const int l = __ffsll((unsigned long long)b) - 1;
-                const uint32_t ulo = __builtin_amdgcn_readlane((uint32_t)U, l);
-                const uint32_t uhi = __builtin_amdgcn_readlane((uint32_t)(U >> 32), l);
-                const uint64_t ul = ((uint64_t)uhi << 32) | ulo;
-                if (lane == (uint32_t)l) {
-                    const uint32_t off = (w - HW) * 64 + (uint32_t)(__ffsll((unsigned long long)ul) - 1);
-                    atomicMin(&s_first[k + 1], off);
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t it = atomicAdd(L.queue, 1u);
+            uint32_t ok = 0, ivi = 0, b = 0, cnt = 0;
+            if (it < L.n_items) {
+                ok = 1;
+                if (L.items) {
+                    const uint4 x = L.items[it];
+                    ivi = x.x;
+                    b = x.y;
+                    cnt = x.z;
+                } else {
+                    const uint64_t ns = L.iv[0].nseg;
+                    b = (uint32_t)((uint64_t)it * ns / L.n_items);
+                    cnt = (uint32_t)((uint64_t)(it + 1) * ns / L.n_items) - b;
                 }
-                found |= 1u << (k + 1);
             }
+            s_item[0] = ivi;
+            s_item[1] = b;
+            s_item[2] = cnt;
+            s_item[3] = ok;
         }
-        if (U) {
-            // still unresolved after the in-LDS steps: exact tail pass
-            uint64_t x = U;
-            while (x) {
-                const int bit = __ffsll((unsigned long long)x) - 1;
-                x &= x - 1;
-                const unsigned long long idx = atomicAdd(&P.acc->tail_count, 1ull);
-                if (idx < P.tail_cap)
-                    P.tail_n[idx] = j0 + (uint64_t)bit;
-                else
-                    atomicOr(&P.acc->status, (unsigned)ESQ_STATUS_TAIL_OVERFLOW);
-            }
-        }
-        if (MODE == 1 && V) {
-            if (U) {
-#pragma unroll
-                for (int i = 0; i < 16; i++)
-                    D[i] &= ~(spread4((uint32_t)(U >> (4 * i)) & 15u) * 0xffu);
-            }
-            store_depths(P.out_mink + ((int64_t)j0 - (int64_t)P.I0), D, V);
-        }
-    }
-
-    // 4. workgroup totals -> call accumulators
-#pragma unroll
-    for (int k = 1; k <= kMaxKh; k++) {
-        if (k > (int)klds)
+        if (tid < kMaxKh + 2)
+            s_first[tid] = kNone;
+        if (tid <= kMaxKh)
+            s_cnt[tid] = 0;
+        __syncthreads();
+        if (!s_item[3])
             break;
-        uint32_t v = cnt[k];
-        for (int o = 32; o > 0; o >>= 1)
-            v += __shfl_xor(v, o);
-        if (lane == 0 && v)
-            atomicAdd(&s_cnt[k], v);
+        const uint32_t ivi = s_item[0], seg0 = s_item[1], nsegs = s_item[2];
+        const Interval IV = L.iv[ivi];
+        const uint32_t cap = L.bucket_cap;
+
+        uint32_t cnt[kMaxKh + 1];
+#pragma unroll
+        for (int k = 0; k <= kMaxKh; k++)
+            cnt[k] = 0;
+        uint32_t found = 0;
+
+        for (uint32_t seg = seg0; seg < seg0 + nsegs; seg++) {
+            const int64_t Bs = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S;
+            const int64_t gw0 = Bs / 64;  // exact: Bs is a multiple of 64
+            const uint32_t wb = (uint32_t)(((uint64_t)IV.wheel_base0 + (uint64_t)seg * wstep) % kWheelPeriod);
+
+            // 1. the wheel pattern (words below odd index 0 are all marked);
+            //    each medium prime's first hit in the region
+            const uint64_t* src = L.wheel + wb;
+            if (gw0 >= 0) {
+                uint32_t w = tid;
+                for (; w + 7 * T < L.rw; w += 8 * T) {
+                    uint64_t v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++)
+                        v[u] = src[w + u * T];
+#pragma unroll
+                    for (int u = 0; u < 8; u++)
+                        bm[w + u * T] = v[u];
+                }
+                for (; w < L.rw; w += T)
+                    bm[w] = src[w];
+            } else {
+                for (uint32_t w = tid; w < L.rw; w += T)
+                    bm[w] = (gw0 + (int64_t)w < 0) ? ~0ull : src[w];
+            }
+            if (seg == seg0) {
+                for (uint32_t i = tid; i < nmed; i += T) {
+                    const uint32_t q = L.medq[i].x;
+                    const int64_t d = (int64_t)((q - 1) >> 1) - Bs;
+                    int64_t f = d % (int64_t)q;
+                    if (f < 0)
+                        f += q;
+                    s_f[i] = (uint32_t)f;
+                }
+            } else {
+                for (uint32_t i = tid; i < nmed; i += T) {
+                    const uint2 qs = L.medq[i];
+                    const uint32_t f = s_f[i];
+                    s_f[i] = f >= qs.y ? f - qs.y : f + qs.x - qs.y;
+                }
+            }
+            __syncthreads();
+
+            // 2. odd multiples of p^2: medium primes by lane-tasks, larger ones
+            //    from the segment's hit slots (directly if the slots overflowed)
+            for (uint32_t e = tid; e < L.n_tasks; e += T) {
+                const MedTask tk = L.tasks[e];
+                const uint32_t v = tk.vc & 0xffffu, c = tk.vc >> 16;
+                const uint64_t p0 = (uint64_t)s_f[tk.idx] + (uint64_t)v * tk.q;
+                if (p0 >= R)
+                    continue;
+                const uint32_t step = c * tk.q;
+                for (uint32_t pos = (uint32_t)p0; pos < R; pos += step)
+                    mark(bm32, pos);
+            }
+            if (L.bucket_cnt) {
+                const uint32_t gs = IV.seg_base + seg;
+                const uint32_t nb = L.bucket_cnt[gs];
+                if (nb <= cap) {
+                    const uint32_t* sl = L.bucket_slot + (uint64_t)gs * cap;
+                    for (uint32_t e = tid; e < nb; e += T) {
+                        const uint32_t pos = sl[e];
+                        if (pos < R)
+                            mark(bm32, pos);
+                    }
+                } else {
+                    // slots overflowed: every prime above the medium range, directly
+                    for (uint32_t pi = L.med_end + tid; pi < IV.pmax_end; pi += T) {
+                        const uint64_t p = L.primes[pi];
+                        const uint64_t q = p * p;
+                        for (uint64_t pos = first_hit(Bs, q); pos < R; pos += q)
+                            mark(bm32, (uint32_t)pos);
+                    }
+                }
+            }
+            __syncthreads();
+
+            if (MODE == 2) {
+                // output word wo = seg * SW + lw covers odd indices I0 + 64 wo ...:
+                // region bits out_shift + 64 lw ... (words lw and lw + 1)
+                const uint32_t sh = IV.out_shift;
+                const uint64_t n_bits = IV.I1 - IV.I0;
+                for (uint32_t lw = tid; lw < SW; lw += T) {
+                    const uint64_t wo = (uint64_t)seg * SW + lw;
+                    if (wo * 64 >= n_bits)
+                        break;
+                    const uint64_t lo = bm[lw], hi = bm[lw + 1];
+                    const uint64_t v = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
+                    uint64_t out = ~v;
+                    const uint64_t rem = n_bits - wo * 64;
+                    if (rem < 64)
+                        out &= (1ull << rem) - 1;
+                    IV.out_bits[wo] = out;
+                }
+                __syncthreads();
+                continue;
+            }
+
+            // 3. Algorithm 2, bit-sliced: U holds the n of one word still
+            //    without a representation; step k keeps the n whose n - 2^k
+            //    (2^(k-1) bits lower) is marked.  cnt[k] counts U after step k;
+            //    s_first[k+1] the least n in it.
+            const uint64_t As = (uint64_t)(IV.A0 + (int64_t)seg * (int64_t)S);
+            // main words wholly inside [I0, I1)
+            const uint64_t lo_w = IV.I0 > As ? (IV.I0 - As + 63) / 64 : 0;
+            const uint64_t hi_w = IV.I1 > As ? min((IV.I1 - As) / 64, (uint64_t)SW) : 0;
+            for (uint32_t mw = tid; mw < SW; mw += T) {
+                const uint32_t w = HW + mw;
+                const uint64_t j0 = As + (uint64_t)mw * 64;
+                const uint64_t V = (mw >= lo_w && mw < hi_w) ? ~0ull : valid_mask(j0, IV.I0, IV.I1);
+                uint64_t U = V;
+                const uint64_t cur = bm[w], prv = bm[w - 1];
+                uint32_t D[16];
+                if (MODE == 1) {
+#pragma unroll
+                    for (int i = 0; i < 16; i++)
+                        D[i] = spread4((uint32_t)(V >> (4 * i)) & 15u);
+                }
+#pragma unroll
+                for (int k = 1; k <= kMaxKh; k++) {
+                    if (k > (int)klds)
+                        break;
+                    uint64_t win;
+                    if (k <= 6) {
+                        const int sh = 1 << (k - 1);
+                        win = (cur << sh) | (prv >> (64 - sh));
+                    } else if (k == 7) {
+                        win = prv;
+                    } else {
+                        win = U ? bm[w - (1u << (k - 7))] : 0ull;
+                    }
+                    U &= win;
+                    cnt[k] += (uint32_t)__popcll(U);
+                    if (MODE == 1) {
+#pragma unroll
+                        for (int i = 0; i < 16; i++)
+                            D[i] += spread4((uint32_t)(U >> (4 * i)) & 15u);
+                    }
+                    const bool track = !(found & (1u << (k + 1)));
+                    if (k >= 3 || track) {
+                        const uint64_t b = __ballot(U != 0);
+                        if (b == 0)
+                            break;
+                        if (track) {
+                            const int l = __ffsll((unsigned long long)b) - 1;
+                            if (lane == (uint32_t)l) {
+                                const uint64_t n_first = j0 + (uint64_t)(__ffsll((unsigned long long)U) - 1);
+                                atomicMin(&s_first[k + 1], (unsigned long long)n_first);
+                            }
+                            found |= 1u << (k + 1);
+                        }
+                    }
+                }
+                if (U) {
+                    // still unresolved after the in-LDS steps: exact tail pass
+                    uint64_t x = U;
+                    atomicAdd(&IV.acc->tail_count, (unsigned long long)__popcll(U));
+                    while (x) {
+                        const int bit = __ffsll((unsigned long long)x) - 1;
+                        x &= x - 1;
+                        const unsigned long long idx = atomicAdd(L.tail_count, 1ull);
+                        if (idx < L.tail_cap) {
+                            L.tail_n[idx] = j0 + (uint64_t)bit;
+                            L.tail_iv[idx] = ivi;
+                        } else {
+                            atomicOr(&IV.acc->status, (unsigned)ESQ_STATUS_TAIL_OVERFLOW);
+                        }
+                    }
+                }
+                if (MODE == 1 && V && IV.out_mink) {
+                    if (U) {
+#pragma unroll
+                        for (int i = 0; i < 16; i++)
+                            D[i] &= ~(spread4((uint32_t)(U >> (4 * i)) & 15u) * 0xffu);
+                    }
+                    store_depths(IV.out_mink + ((int64_t)j0 - (int64_t)IV.I0), D, V);
+                }
+            }
+            __syncthreads();
+        }
+
+        // 4. the item's totals -> the interval's accumulators
+        if (MODE != 2) {
+#pragma unroll
+            for (int k = 1; k <= kMaxKh; k++) {
+                if (k > (int)klds)
+                    break;
+                uint32_t v = cnt[k];
+                for (int o = 32; o > 0; o >>= 1)
+                    v += __shfl_xor(v, o);
+                if (lane == 0 && v)
+                    atomicAdd(&s_cnt[k], v);
+            }
+            __syncthreads();
+            if (tid >= 1 && tid <= klds && s_cnt[tid])
+                atomicAdd(&IV.acc->cnt[tid], (unsigned long long)s_cnt[tid]);
+            if (tid >= 2 && tid <= klds + 1 && s_first[tid] != kNone)
+                atomicMin(&IV.acc->first[tid], s_first[tid]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (tid >= 1 && tid <= klds && s_cnt[tid])
-        atomicAdd(&P.acc->cnt[tid], (unsigned long long)s_cnt[tid]);
-    if (tid >= 2 && tid <= klds + 1 && s_first[tid] != kNone32)
-        atomicMin(&P.acc->first[tid], (unsigned long long)(As + s_first[tid]));
 }
 
-hipError_t launch_segment(const SegParams& p, int mode, uint32_t block, hipStream_t s)
+hipError_t launch_verify(const Launch& L, uint32_t grid, uint32_t block, hipStream_t s)
 {
-    const size_t lds = (size_t)p.rw * 8;
-    if (p.nseg == 0)
+    const size_t lds = (size_t)L.rw * 8;
+    if (grid == 0 || L.n_items == 0)
         return hipSuccess;
-    switch (mode) {
+    switch (L.mode) {
     case 0:
-        hipLaunchKernelGGL(k_segment<0>, dim3(p.nseg), dim3(block), lds, s, p);
+        hipLaunchKernelGGL(k_verify<0>, dim3(grid), dim3(block), lds, s, L);
         break;
     case 1:
-        hipLaunchKernelGGL(k_segment<1>, dim3(p.nseg), dim3(block), lds, s, p);
+        hipLaunchKernelGGL(k_verify<1>, dim3(grid), dim3(block), lds, s, L);
         break;
     default:
-        hipLaunchKernelGGL(k_segment<2>, dim3(p.nseg), dim3(block), lds, s, p);
+        hipLaunchKernelGGL(k_verify<2>, dim3(grid), dim3(block), lds, s, L);
         break;
     }
     return hipGetLastError();
+}
+
+int verify_occupancy(uint32_t block, size_t lds_bytes)
+{
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_verify<0>, (int)block, lds_bytes) !=
+        hipSuccess)
+        return 1;
+    return occ > 0 ? occ : 1;
+}
+
+size_t verify_static_lds()
+{
+    return sizeof(uint32_t) * kMaxMedium + sizeof(unsigned long long) * (kMaxKh + 2) +
+           sizeof(uint32_t) * (kMaxKh + 1) + 16;
 }
 
 // --------------------------------------------------------------- tail
 
 // Exact search, by trial division over the resident prime squares, for the
 // n whose first k_lds candidates were all marked (Algorithm 2 continued).
-__global__ __launch_bounds__(256) void k_tail(TailParams P)
+__global__ __launch_bounds__(256) void k_tail(Launch L)
 {
     __shared__ int s_hit;
-    const unsigned long long total = P.acc->tail_count;
-    const uint64_t count = total < P.tail_cap ? total : P.tail_cap;
+    const unsigned long long total = *L.tail_count;
+    const uint64_t count = total < L.tail_cap ? total : L.tail_cap;
     volatile int* hitp = &s_hit;
     for (uint64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const uint64_t j = P.tail_n[idx];
+        const uint64_t j = L.tail_n[idx];
+        const Interval IV = L.iv[L.tail_iv[idx]];
         const uint64_t n = 2 * j + 1;
         uint32_t d = 0;
-        for (uint32_t k = P.k_lds + 1; k <= 63; k++) {
-            if (k > P.kmax_eff)
+        for (uint32_t k = L.k_lds + 1; k <= 63; k++) {
+            if (k > L.kmax_eff)
                 break;
             const uint64_t pk = 1ull << k;
             if (pk >= n)
@@ -469,8 +569,8 @@ __global__ __launch_bounds__(256) void k_tail(TailParams P)
             if (threadIdx.x == 0)
                 *hitp = 0;
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < P.nprimes; i += blockDim.x) {
-                const uint64_t pr = P.primes[i];
+            for (uint32_t i = threadIdx.x; i < L.nprimes; i += blockDim.x) {
+                const uint64_t pr = L.primes[i];
                 const uint64_t q = pr * pr;
                 if (q > m || *hitp)
                     break;
@@ -488,20 +588,20 @@ __global__ __launch_bounds__(256) void k_tail(TailParams P)
             }
         }
         if (threadIdx.x == 0) {
-            P.tail_d[idx] = (uint8_t)d;
-            atomicAdd(&P.acc->deep_hist[d], 1ull);
+            L.tail_d[idx] = (uint8_t)d;
+            atomicAdd(&IV.acc->deep_hist[d], 1ull);
             const uint32_t top = d ? d : 64u;
-            for (uint32_t kk = P.k_lds + 2; kk <= top; kk++)
-                atomicMin(&P.acc->first[kk], (unsigned long long)j);
-            if (P.out_mink)
-                P.out_mink[j - P.I0] = (uint8_t)d;
+            for (uint32_t kk = L.k_lds + 2; kk <= top; kk++)
+                atomicMin(&IV.acc->first[kk], (unsigned long long)j);
+            if (IV.out_mink)
+                IV.out_mink[j - IV.I0] = (uint8_t)d;
         }
     }
 }
 
-hipError_t launch_tail(const TailParams& p, hipStream_t s)
+hipError_t launch_tail(const Launch& L, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tail, dim3(512), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_tail, dim3(512), dim3(256), 0, s, L);
     return hipGetLastError();
 }
 
@@ -522,20 +622,29 @@ __device__ unsigned long long block_sum(unsigned long long v, unsigned long long
     return r;
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(FinParams P)
+// One workgroup per interval.
+__global__ __launch_bounds__(1024) void k_finalize(Launch L, void* out_summaries, void* out_records,
+                                                   uint64_t* out_exceptions, uint64_t exc_cap)
 {
     extern __shared__ unsigned long long s_sort[];
     __shared__ unsigned long long s_acc;
     __shared__ unsigned int s_fill;
-    const Acc* A = P.acc;
+    __shared__ unsigned long long s_first[65];
+    const uint32_t ivi = blockIdx.x;
+    const Interval IV = L.iv[ivi];
+    const Acc* A = IV.acc;
     const uint32_t tid = threadIdx.x, T = blockDim.x;
-    const unsigned long long tail_total = A->tail_count;
-    const uint64_t nlist = tail_total < P.tail_cap ? tail_total : P.tail_cap;
+    const unsigned long long tail_total = *L.tail_count;
+    const uint64_t nlist = tail_total < L.tail_cap ? tail_total : L.tail_cap;
+    const uint64_t n_odd = IV.I1 - IV.I0;
     const uint64_t n_exc = A->deep_hist[0];
-    const uint64_t want = n_exc < P.exc_cap ? n_exc : P.exc_cap;
+    const uint64_t want = n_exc < exc_cap ? n_exc : exc_cap;
+    for (uint32_t i = tid; i < 65; i += T)
+        s_first[i] = A->first[i];
 
-    if (P.out_exceptions && want > 0) {
-        // the want-th smallest exception (binary search on its odd index)
+    if (out_exceptions && want > 0) {
+        // the want-th smallest exception of this interval (binary search on
+        // its odd index), then an LDS sort of those up to it
         uint64_t thr = kNone;
         if (want < n_exc) {
             uint64_t lo = 0, hi = 1ull << 56;
@@ -543,7 +652,7 @@ __global__ __launch_bounds__(1024) void k_finalize(FinParams P)
                 const uint64_t mid = lo + (hi - lo) / 2;
                 unsigned long long c = 0;
                 for (uint64_t i = tid; i < nlist; i += T)
-                    c += (P.tail_d[i] == 0 && P.tail_n[i] <= mid) ? 1ull : 0ull;
+                    c += (L.tail_iv[i] == ivi && L.tail_d[i] == 0 && L.tail_n[i] <= mid) ? 1ull : 0ull;
                 c = block_sum(c, &s_acc);
                 if (c >= want)
                     hi = mid;
@@ -556,10 +665,10 @@ __global__ __launch_bounds__(1024) void k_finalize(FinParams P)
             s_fill = 0;
         __syncthreads();
         for (uint64_t i = tid; i < nlist; i += T)
-            if (P.tail_d[i] == 0 && P.tail_n[i] <= thr) {
+            if (L.tail_iv[i] == ivi && L.tail_d[i] == 0 && L.tail_n[i] <= thr) {
                 const unsigned int slot = atomicAdd(&s_fill, 1u);
                 if (slot < kFinalizeSortCap)
-                    s_sort[slot] = P.tail_n[i];
+                    s_sort[slot] = L.tail_n[i];
             }
         __syncthreads();
         const uint32_t got = min(s_fill, kFinalizeSortCap);
@@ -585,22 +694,23 @@ __global__ __launch_bounds__(1024) void k_finalize(FinParams P)
                 __syncthreads();
             }
         for (uint32_t i = tid; i < want && i < got; i += T)
-            P.out_exceptions[i] = 2 * s_sort[i] + 1;
+            out_exceptions[i] = 2 * s_sort[i] + 1;
     }
+    __syncthreads();
 
     if (tid != 0)
         return;
-    esq_summary* out = reinterpret_cast<esq_summary*>(P.out_summary);
+    esq_summary* out = reinterpret_cast<esq_summary*>(out_summaries) + ivi;
     unsigned long long h[65];
     for (int k = 0; k < 65; k++)
         h[k] = 0;
-    unsigned long long prev = P.n_odd;
-    for (uint32_t k = 1; k <= P.k_lds; k++) {
+    unsigned long long prev = n_odd;
+    for (uint32_t k = 1; k <= L.k_lds; k++) {
         const unsigned long long c = A->cnt[k];
         h[k] = prev - c;
         prev = c;
     }
-    for (uint32_t k = P.k_lds + 1; k < 65; k++)
+    for (uint32_t k = L.k_lds + 1; k < 65; k++)
         h[k] += A->deep_hist[k];
     h[0] = A->deep_hist[0];
     unsigned long long ksum = 0;
@@ -612,16 +722,17 @@ __global__ __launch_bounds__(1024) void k_finalize(FinParams P)
     }
     // record-setters: first[k] = least n-index with depth >= k; each distinct
     // value is a record, labelled with the deepest level sharing it
-    esq_record* rec = reinterpret_cast<esq_record*>(P.out_records);
+    esq_record* rec = out_records ? reinterpret_cast<esq_record*>(out_records) + (uint64_t)ivi * ESQ_RECORDS_CAP
+                                  : nullptr;
     uint32_t nrec = 0;
-    if (P.n_odd) {
+    if (n_odd) {
         uint32_t k = 1;
         while (k <= 64) {
-            const unsigned long long v = (k == 1) ? P.I0 : A->first[k];
+            const unsigned long long v = (k == 1) ? IV.I0 : s_first[k];
             if (v == kNone)
                 break;
             uint32_t kk = k;
-            while (kk < 64 && A->first[kk + 1] == v)
+            while (kk < 64 && s_first[kk + 1] == v)
                 kk++;
             if (rec && nrec < ESQ_RECORDS_CAP) {
                 rec[nrec].n = 2 * v + 1;
@@ -632,33 +743,38 @@ __global__ __launch_bounds__(1024) void k_finalize(FinParams P)
             k = kk + 1;
         }
     }
-    out->n0 = P.n_odd ? 2 * P.I0 + 1 : 0;
-    out->n_odd = P.n_odd;
+    out->n0 = n_odd ? 2 * IV.I0 + 1 : 0;
+    out->n_odd = n_odd;
     for (int k = 0; k < 65; k++)
         out->hist[k] = h[k];
     out->ksum = ksum;
     out->kmax_seen = kseen;
     out->n_records = nrec < ESQ_RECORDS_CAP ? nrec : ESQ_RECORDS_CAP;
     out->n_exceptions = h[0];
-    out->status = A->status | (tail_total > P.tail_cap ? ESQ_STATUS_TAIL_OVERFLOW : 0u);
+    out->status = A->status;
     out->reserved = 0;
 }
 
-hipError_t launch_finalize(const FinParams& p, hipStream_t s)
+hipError_t launch_finalize(const Launch& L, void* out_summaries, void* out_records,
+                           uint64_t* out_exceptions, uint64_t exc_cap, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), (size_t)kFinalizeSortCap * 8, s, p);
+    if (L.n_iv == 0)
+        return hipSuccess;
+    const size_t lds = out_exceptions ? (size_t)kFinalizeSortCap * 8 : 0;
+    hipLaunchKernelGGL(k_finalize, dim3(L.n_iv), dim3(out_exceptions ? 1024 : 64), lds, s, L,
+                       out_summaries, out_records, out_exceptions, exc_cap);
     return hipGetLastError();
 }
 
 hipError_t configure_kernels()
 {
     hipError_t e;
-    const int lds_max = 160 * 1024 - 8 * 1024;
-    e = hipFuncSetAttribute((const void*)k_segment<0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    const int lds_max = 160 * 1024 - (int)verify_static_lds() - 1024;
+    e = hipFuncSetAttribute((const void*)k_verify<0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_segment<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    e = hipFuncSetAttribute((const void*)k_verify<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_segment<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    e = hipFuncSetAttribute((const void*)k_verify<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_finalize, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(kFinalizeSortCap * 8));

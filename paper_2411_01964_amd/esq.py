@@ -23,8 +23,10 @@ STATUS_TAIL_OVERFLOW = 1
 STATUS_BUCKET_OVERFLOW = 2
 
 # every function declared in include/esq.h
-EXPORTS = ("esq_init", "esq_sieve_segment", "esq_verify_range", "esq_set_param",
-           "esq_get_param", "esq_profile_take", "esq_last_error", "esq_shutdown")
+EXPORTS = ("esq_init", "esq_sieve_segment", "esq_verify_range", "esq_verify_batch",
+           "esq_batch_create", "esq_batch_launch", "esq_batch_destroy",
+           "esq_set_param", "esq_get_param", "esq_profile_take", "esq_last_error",
+           "esq_shutdown")
 
 
 class Summary(ctypes.Structure):
@@ -75,6 +77,14 @@ def lib():
         L.esq_sieve_segment.restype = ctypes.c_int
         L.esq_verify_range.argtypes = [u64, u64, u32, vp, vp, vp, vp, u64, vp]
         L.esq_verify_range.restype = ctypes.c_int
+        L.esq_verify_batch.argtypes = [u32, vp, vp, u32, vp, vp, vp, vp]
+        L.esq_verify_batch.restype = ctypes.c_int
+        L.esq_batch_create.argtypes = [u32, vp, vp, u32, vp, vp, vp, ctypes.POINTER(vp)]
+        L.esq_batch_create.restype = ctypes.c_int
+        L.esq_batch_launch.argtypes = [vp, ctypes.c_int, vp]
+        L.esq_batch_launch.restype = ctypes.c_int
+        L.esq_batch_destroy.argtypes = [vp]
+        L.esq_batch_destroy.restype = None
         L.esq_set_param.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         L.esq_set_param.restype = ctypes.c_int
         L.esq_get_param.argtypes = [ctypes.c_char_p]
@@ -155,10 +165,10 @@ class Pending:
         n0 = max(self.lo, 3) | 1
         self.n_odd = (self.hi - n0 + 1) // 2 if self.hi > n0 else 0
         dev = torch.device("cuda", torch.cuda.current_device())
-        self.summary = torch.zeros(SUMMARY_BYTES, dtype=torch.uint8, device=dev)
-        self.records = torch.zeros(ESQ_RECORDS_CAP * RECORD_BYTES, dtype=torch.uint8, device=dev)
+        self.summary = torch.empty(SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+        self.records = torch.empty(ESQ_RECORDS_CAP * RECORD_BYTES, dtype=torch.uint8, device=dev)
         self.exc_cap = int(exceptions_cap)
-        self.exceptions = (torch.zeros(self.exc_cap, dtype=torch.int64, device=dev)
+        self.exceptions = (torch.empty(self.exc_cap, dtype=torch.int64, device=dev)
                            if self.exc_cap else None)
         self.per_n = (torch.empty(max(self.n_odd, 1), dtype=torch.uint8, device=dev)
                       if per_n else None)
@@ -213,3 +223,136 @@ def verify_range(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None, che
     (per-k counts, sum of k, maximum k, record-setters, exceptions).  With
     per_n=True the result holds "per_n", a uint8 CUDA tensor of least k."""
     return verify_range_async(lo, hi, kmax, per_n, exceptions_cap, stream).result(check=check)
+
+
+def _parse(summary_bytes, record_bytes):
+    s = Summary.from_buffer_copy(summary_bytes)
+    nrec = min(s.n_records, ESQ_RECORDS_CAP)
+    recs = []
+    for i in range(nrec):
+        r = Record.from_buffer_copy(record_bytes[i * RECORD_BYTES:(i + 1) * RECORD_BYTES])
+        recs.append((int(r.n), int(r.k)))
+    return {
+        "n0": int(s.n0),
+        "n_odd": int(s.n_odd),
+        "hist": [int(x) for x in s.hist],
+        "ksum": int(s.ksum),
+        "kmax_seen": int(s.kmax_seen),
+        "n_records": int(s.n_records),
+        "records": recs,
+        "n_exceptions": int(s.n_exceptions),
+        "status": int(s.status),
+    }
+
+
+class PendingBatch:
+    """Device buffers of one enqueued esq_verify_batch call."""
+
+    def __init__(self, los, his, kmax, per_n, stream):
+        import numpy as np
+        self.lo = np.ascontiguousarray(np.asarray(los, dtype=np.uint64))
+        self.hi = np.ascontiguousarray(np.asarray(his, dtype=np.uint64))
+        if self.lo.shape != self.hi.shape or self.lo.ndim != 1:
+            raise ValueError("lo and hi must be 1-D of equal length")
+        self.count = int(self.lo.size)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.summaries = torch.empty(max(self.count, 1) * SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+        self.records = torch.empty(max(self.count, 1) * ESQ_RECORDS_CAP * RECORD_BYTES,
+                                   dtype=torch.uint8, device=dev)
+        self.per_n = None
+        ptrs = None
+        if per_n is not None and any(per_n):
+            self.per_n = []
+            ptrs = (ctypes.c_void_p * self.count)()
+            for i in range(self.count):
+                if per_n[i]:
+                    n0 = max(int(self.lo[i]), 3) | 1
+                    n_odd = (int(self.hi[i]) - n0 + 1) // 2 if int(self.hi[i]) > n0 else 0
+                    t = torch.empty(max(n_odd, 1), dtype=torch.uint8, device=dev)
+                    self.per_n.append(t[:n_odd])
+                    ptrs[i] = t.data_ptr()
+                else:
+                    self.per_n.append(None)
+                    ptrs[i] = None
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().esq_verify_batch(
+            self.count, ctypes.c_void_p(self.lo.ctypes.data), ctypes.c_void_p(self.hi.ctypes.data),
+            int(kmax), ptrs, _ptr(self.summaries), _ptr(self.records),
+            ctypes.c_void_p(self.stream.cuda_stream)))
+        self.event = torch.cuda.Event()
+        self.event.record(self.stream)
+
+    def done(self) -> bool:
+        return self.event.query()
+
+    def result(self, check: bool = True) -> list:
+        self.event.synchronize()
+        sb = self.summaries.cpu().numpy().tobytes()
+        rb = self.records.cpu().numpy().tobytes()
+        out = []
+        rstride = ESQ_RECORDS_CAP * RECORD_BYTES
+        for i in range(self.count):
+            r = _parse(sb[i * SUMMARY_BYTES:(i + 1) * SUMMARY_BYTES], rb[i * rstride:(i + 1) * rstride])
+            if self.per_n is not None and self.per_n[i] is not None:
+                r["per_n"] = self.per_n[i]
+            if check and r["status"]:
+                raise EsqError(-100, "device status 0x%x for interval %d" % (r["status"], i))
+            out.append(r)
+        return out
+
+
+def verify_batch_async(los, his, kmax=0, per_n=None, stream=None) -> PendingBatch:
+    """Enqueue many intervals in one launch (esq_verify_batch)."""
+    return PendingBatch(los, his, kmax, per_n, stream)
+
+
+def verify_batch(los, his, kmax=0, per_n=None, stream=None, check=True) -> list:
+    """Per-interval results of esq_verify_batch, in input order."""
+    return verify_batch_async(los, his, kmax, per_n, stream).result(check=check)
+
+
+class PreparedBatch:
+    """A batch planned once (esq_batch_create) and launched many times, as
+    plain launches or as a replayed hipGraph (esq_batch_launch)."""
+
+    def __init__(self, los, his, kmax=0):
+        import numpy as np
+        self.lo = np.ascontiguousarray(np.asarray(los, dtype=np.uint64))
+        self.hi = np.ascontiguousarray(np.asarray(his, dtype=np.uint64))
+        self.count = int(self.lo.size)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.summaries = torch.empty(self.count * SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+        self.records = torch.empty(self.count * ESQ_RECORDS_CAP * RECORD_BYTES,
+                                   dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p(None)
+        _check(lib().esq_batch_create(self.count, ctypes.c_void_p(self.lo.ctypes.data),
+                                      ctypes.c_void_p(self.hi.ctypes.data), int(kmax), None,
+                                      _ptr(self.summaries), _ptr(self.records), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, graph=False, stream=None):
+        _check(lib().esq_batch_launch(self.handle, 1 if graph else 0, _stream(stream)))
+
+    def results(self, check=True):
+        torch.cuda.synchronize()
+        sb = self.summaries.cpu().numpy().tobytes()
+        rb = self.records.cpu().numpy().tobytes()
+        rstride = ESQ_RECORDS_CAP * RECORD_BYTES
+        out = []
+        for i in range(self.count):
+            r = _parse(sb[i * SUMMARY_BYTES:(i + 1) * SUMMARY_BYTES], rb[i * rstride:(i + 1) * rstride])
+            if check and r["status"]:
+                raise EsqError(-100, "device status 0x%x for interval %d" % (r["status"], i))
+            out.append(r)
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().esq_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,116 @@
+"""The batched form (many intervals in one persistent launch with a device work
+queue) gives, per interval, exactly what the interval gives alone, and what
+the oracle gives."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_01964_amd import esq, workloads
+
+pytestmark = pytest.mark.gpu
+DEFAULTS = dict(seg_log2=18, kh=13, block=256, entry_hits=16, tail_cap=1 << 20,
+                medium_max=8191, bucket_cap=0, items_per_wg=4)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib_ready():
+    esq.init(0, (1 << 50) + (1 << 33))
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+    yield
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+
+
+KEYS = ("n0", "n_odd", "hist", "ksum", "kmax_seen", "records", "n_records", "n_exceptions")
+
+
+def same(a, b):
+    for k in KEYS:
+        assert a[k] == b[k], k
+
+
+def mixed_intervals(seed, count, log2_len=(4, 17)):
+    lo, hi = workloads.batch_intervals(seed=seed, count=count, log2_len=log2_len,
+                                       start_range=(3, 1 << 50))
+    # edge cases: empty, tiny, near zero, even bounds, overlapping another entry
+    lo += [3, 0, 10, 1 << 40, 1 << 20, lo[0]]
+    hi += [3, 4, 11, (1 << 40) + 2, (1 << 20) + 1000, hi[0]]
+    return lo, hi
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(seg_log2=12, items_per_wg=1), dict(kh=4),
+                                 dict(bucket_cap=1, medium_max=101)])
+def test_batch_equals_alone(kw):
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, kw.get(k, v))
+    lo, hi = mixed_intervals(41, 40)
+    per_n = [i % 3 == 0 for i in range(len(lo))]
+    batch = esq.verify_batch(lo, hi, per_n=per_n)
+    assert len(batch) == len(lo)
+    for i, (a, b) in enumerate(zip(lo, hi)):
+        alone = esq.verify_range(a, b, per_n=per_n[i])
+        same(batch[i], alone)
+        if per_n[i]:
+            assert torch.equal(batch[i]["per_n"], alone["per_n"]), i
+
+
+def test_batch_vs_oracle():
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+    lo, hi = workloads.batch_intervals(seed=43, count=12, log2_len=(6, 12),
+                                       start_range=(1 << 30, 1 << 44))
+    batch = esq.verify_batch(lo, hi, per_n=[True] * len(lo))
+    for i, (a, b) in enumerate(zip(lo, hi)):
+        o = oracle.verify_range(a, b, per_n=True)
+        same(batch[i], o)
+        assert np.array_equal(batch[i]["per_n"].cpu().numpy(), o["per_n"]), i
+
+
+def test_batch_kmax_and_repeat():
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+    lo, hi = mixed_intervals(44, 20, log2_len=(8, 14))
+    a = esq.verify_batch(lo, hi, kmax=2)
+    b = esq.verify_batch(lo, hi, kmax=2)
+    for i, (x, y) in enumerate(zip(lo, hi)):
+        same(a[i], b[i])
+        same(a[i], esq.verify_range(x, y, kmax=2))
+
+
+def test_batch_config4_sample_equals_alone():
+    """The first 32 intervals of the seeded 4096-interval workload (lengths
+    2^16..2^28, starts in [2^30, 2^50)), batched vs alone."""
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+    lo, hi = workloads.batch_intervals(seed=4, count=4096)
+    lo, hi = lo[:32], hi[:32]
+    batch = esq.verify_batch(lo, hi)
+    for i, (a, b) in enumerate(zip(lo, hi)):
+        same(batch[i], esq.verify_range(a, b))
+
+
+def test_prepared_batch_and_graph_replays():
+    """A prepared batch launched plainly and as a replayed hipGraph, with
+    eager work and synchronisations between replays: every replay equals the
+    eager result."""
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+    lo, hi = mixed_intervals(45, 24, log2_len=(8, 16))
+    eager = esq.verify_batch(lo, hi)
+    pb = esq.PreparedBatch(lo, hi)
+    try:
+        pb.launch(graph=False)
+        for i, r in enumerate(pb.results()):
+            same(r, eager[i])
+        side = torch.cuda.Stream()
+        for rep in range(3):
+            pb.launch(graph=True, stream=side if rep % 2 else None)
+            torch.cuda.synchronize()
+            x = esq.verify_range(lo[rep], hi[rep])       # eager work in between
+            same(x, eager[rep])
+            for i, r in enumerate(pb.results()):
+                same(r, eager[i])
+    finally:
+        pb.close()
