@@ -144,6 +144,10 @@ def main():
     ap.add_argument("--workload", default="cfg3_near_2pow50")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--knobs", default="",
+                    help="comma-separated name=value library knobs, e.g. seg_log2=17,block=512")
+    ap.add_argument("--tune", action="store_true",
+                    help="sweep the knobs on the workload first and use the fastest")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (4096 intervals) and served (Poisson) measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -174,6 +178,14 @@ def main():
     n_odd = (hi - n0 + 1) // 2
     log("init")
     esq.init(0, hi + 64)
+    if args.knobs:
+        for kv in args.knobs.split(","):
+            k, v = kv.split("=")
+            esq.set_param(k.strip(), int(v))
+    if args.tune:
+        from paper_2411_01964_amd import tune
+        best, t = tune.tune_range(lo, hi, reps=5)
+        log("tuned: %s (%.3f ms)" % (best, t * 1e3))
     log("warmup x%d over %d odd n" % (args.warmup, n_odd))
     ref = None
     for _ in range(args.warmup):
@@ -241,6 +253,7 @@ def main():
             "seg_log2": esq.get_param("seg_log2"),
             "kh": esq.get_param("kh"),
             "block": esq.get_param("block"),
+            "medium_max": esq.get_param("medium_max"),
         },
         "roofline": roof,
         "roofline_alt": alt,

@@ -38,17 +38,17 @@ int hip_fail(hipError_t e, const char* what)
 struct Params {
     int seg_log2 = 18;
     int kh = 13;
-    int block = 256;
+    int block = 512;
     int entry_hits = 16;
     int64_t tail_cap = 1 << 20;
     int profile = 0;
-    int64_t medium_max = 8191;  // largest prime marked per segment (others: hit slots)
+    int64_t medium_max = 4095;  // largest prime marked per segment (others: hit slots)
     int64_t bucket_cap = 0;     // hit slots per segment; 0 = from the expected count
     int64_t items_per_wg = 4;   // batch: work items per resident workgroup
 };
 
 struct MedTable {
-    MedTask* tasks = nullptr;
+    uint2* tasks = nullptr;
     uint2* medq = nullptr;
     uint32_t n_tasks = 0;
 };
@@ -246,7 +246,7 @@ int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_
     const uint64_t R = (uint64_t)rw * 64;
     const uint64_t S = 1ull << log2S;
     const uint32_t nmed = med_end - 4;
-    std::vector<std::pair<uint64_t, MedTask>> tasks;
+    std::vector<std::pair<uint64_t, uint2>> tasks;
     std::vector<uint2> medq(std::max<uint32_t>(nmed, 1));
     for (uint32_t i = 0; i < nmed; i++) {
         const uint64_t p = c->primes[4 + i];
@@ -257,18 +257,16 @@ int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_
         uint64_t parts = std::max<uint64_t>(1, (h + entry_hits - 1) / entry_hits);
         parts = std::min<uint64_t>(parts, 65535);
         for (uint64_t v = 0; v < parts; v++) {
-            MedTask t;
-            t.q = (uint32_t)q;
-            t.idx = i;
-            t.vc = (uint32_t)v | ((uint32_t)parts << 16);
-            t.pad = 0;
+            uint2 t;
+            t.x = i | ((uint32_t)v << 16);
+            t.y = (uint32_t)parts;
             tasks.push_back({(h + parts - 1) / parts, t});
         }
     }
     // lanes of one wave get tasks of similar length
     std::stable_sort(tasks.begin(), tasks.end(),
                      [](const auto& a, const auto& b) { return a.first > b.first; });
-    std::vector<MedTask> host(tasks.size());
+    std::vector<uint2> host(tasks.size());
     for (size_t i = 0; i < tasks.size(); i++)
         host[i] = tasks[i].second;
     MedTable t;
@@ -282,11 +280,11 @@ int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_
         return hip_fail(e, "hipMemcpy(medium primes)");
     }
     if (t.n_tasks) {
-        if ((e = hipMalloc(&t.tasks, host.size() * sizeof(MedTask))) != hipSuccess) {
+        if ((e = hipMalloc(&t.tasks, host.size() * sizeof(uint2))) != hipSuccess) {
             (void)hipFree(t.medq);
             return hip_fail(e, "hipMalloc(medium tasks)");
         }
-        if ((e = hipMemcpy(t.tasks, host.data(), host.size() * sizeof(MedTask),
+        if ((e = hipMemcpy(t.tasks, host.data(), host.size() * sizeof(uint2),
                            hipMemcpyHostToDevice)) != hipSuccess) {
             (void)hipFree(t.medq);
             (void)hipFree(t.tasks);
@@ -336,7 +334,7 @@ struct Planned {
     int mode = 0;
     std::vector<Interval> ivs;
     std::vector<uint4> items;
-    uint32_t max_direct = 0, max_cof = 0, grid = 0, block = 256;
+    uint32_t n_heavy = 0, max_direct = 0, max_cof = 0, grid = 0, block = 256;
     bool any_bucket = false;
     uint64_t nseg_total = 0;
     size_t bytes = 0, o_iv = 0, o_acc = 0, o_items = 0, o_bcnt = 0, o_bslot = 0, o_misc = 0;
@@ -408,6 +406,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     uint32_t max_direct = 0, max_cof = 0;
     bool any_bucket = false;
     uint32_t pmax_end_all = med_end;
+    uint64_t E_max = 0;
     for (uint32_t i = 0; i < n_iv; i++) {
         Interval& v = ivs[i];
         if (!v.nseg)
@@ -426,6 +425,15 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
             any_bucket = true;
         max_direct = std::max(max_direct, v.b_direct_end - med_end);
         max_cof = std::max(max_cof, v.n_cof);
+        E_max = std::max(E_max, (uint64_t)(v.nseg - 1) * S + R);
+    }
+    // bucket primes with more than 8 hits in the longest interval get a
+    // group of lanes each
+    uint32_t n_heavy = 0;
+    if (any_bucket) {
+        const uint32_t heavy_end = prime_upper(c, isqrt_u64(E_max / 8));
+        n_heavy = heavy_end > med_end ? std::min(heavy_end - med_end, max_direct) : 0;
+        max_direct -= n_heavy;
     }
 
     MedTable* mt = nullptr;
@@ -444,8 +452,17 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
         }
     }
 
+    // LDS of the segment kernel: bitmap + medium-prime tables (+ tasks if they fit)
+    const size_t nmed = med_end - 4;
+    const size_t lds_base = (size_t)rw * 8 + nmed * 8 + ((nmed + 1) / 2) * 8;
+    if (lds_base > kVerifyLdsMax)
+        return fail(ESQ_EINVAL, "segment too large for LDS with these medium primes");
+    const uint32_t n_tasks = mt ? mt->n_tasks : 0;
+    const bool tasks_in_lds = lds_base + (size_t)n_tasks * 8 <= kVerifyLdsMax;
+    const size_t lds_bytes = lds_base + (tasks_in_lds ? (size_t)n_tasks * 8 : 0);
+
     // work items: runs of consecutive segments
-    const int occ = verify_occupancy((uint32_t)par.block, (size_t)rw * 8);
+    const int occ = verify_occupancy((uint32_t)par.block, lds_bytes);
     const uint64_t resident = (uint64_t)c->n_cu * (uint64_t)occ;
     std::vector<uint4>& items = P->items;
     items.clear();
@@ -500,7 +517,8 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.n_items = n_items;
     L.mode = (uint32_t)mode;
     L.med_end = med_end;
-    L.n_tasks = mt ? mt->n_tasks : 0;
+    L.n_tasks = n_tasks;
+    L.tasks_in_lds = tasks_in_lds ? 1u : 0u;
     L.k_lds = mode == 2 ? 0 : klds;
     L.kmax_eff = kmax_eff;
     L.bucket_cap = cap;
@@ -511,6 +529,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.wheel = c->d_wheel;
     L.tail_cap = tail_cap;
     P->mode = mode;
+    P->n_heavy = n_heavy;
     P->max_direct = max_direct;
     P->max_cof = max_cof;
     P->any_bucket = any_bucket;
@@ -551,7 +570,7 @@ int launch_seq(const Planned& P, bool iv_by_value, bool profile, void* out_summa
     if ((e = launch_prepare(L, accs, iv_by_value ? &P.ivs[0] : nullptr, (uint32_t)P.nseg_total,
                             s)) != hipSuccess)
         return hip_fail(e, "k_prepare");
-    if (P.any_bucket && (e = launch_bucket(L, P.max_direct, P.max_cof, s)) != hipSuccess)
+    if (P.any_bucket && (e = launch_bucket(L, P.n_heavy, P.max_direct, P.max_cof, s)) != hipSuccess)
         return hip_fail(e, "k_bucket");
     std::pair<hipEvent_t, hipEvent_t> ev;
     if (profile && (rc = prof_begin(s, &ev)))

@@ -22,7 +22,7 @@
 
 namespace esq {
 
-constexpr uint32_t kWheelPeriod = 9u * 25u * 49u * 121u;  // 1334025
+constexpr uint32_t kWheelPeriod = 9u * 25u * 49u;  // 11025 words: the table stays in L2
 constexpr uint32_t kWheelExtra = 16640;   // >= largest region in 64-bit words
 constexpr int kMaxKh = 13;                // deepest in-LDS level supported
 constexpr int kMaxMedium = 1536;          // medium primes per launch (LDS offsets)
@@ -59,13 +59,8 @@ struct Interval {
     uint32_t pad;
 };
 
-// Medium-prime lane-task: marks f + (v + c t) q, t >= 0, of prime idx.
-struct MedTask {
-    uint32_t q;     // p^2
-    uint32_t idx;   // medium prime index (0 = the prime 13)
-    uint32_t vc;    // v | (c << 16)
-    uint32_t pad;
-};
+// Medium-prime lane-task, packed in a uint2: x = idx | (v << 16), y = c;
+// it marks f + (v + c t) q, t >= 0, of medium prime idx (0 = the prime 13).
 
 // Geometry and resources shared by every interval of a launch.
 struct Launch {
@@ -84,7 +79,8 @@ struct Launch {
     const uint4* items;           // (interval, first segment, segments, 0), or null
     const uint32_t* primes;       // odd primes ascending
     const uint2* medq;            // per medium prime: (q, S mod q)
-    const MedTask* tasks;
+    const uint2* tasks;           // medium-prime lane-tasks
+    uint32_t tasks_in_lds;        // 1: the task table is copied into LDS
     const uint64_t* wheel;        // kWheelPeriod + kWheelExtra words
     uint32_t* bucket_cnt;         // per global segment
     uint32_t* bucket_slot;        // bucket_cap per global segment
@@ -100,13 +96,15 @@ struct Launch {
 hipError_t launch_wheel_build(uint64_t* wheel, hipStream_t s);
 hipError_t launch_prepare(const Launch& L, Acc* accs, const Interval* iv_single,
                           uint32_t nseg_total, hipStream_t s);
-hipError_t launch_bucket(const Launch& L, uint32_t max_direct, uint32_t max_cof, hipStream_t s);
+hipError_t launch_bucket(const Launch& L, uint32_t n_heavy, uint32_t max_direct, uint32_t max_cof,
+                         hipStream_t s);
 hipError_t launch_verify(const Launch& L, uint32_t grid, uint32_t block, hipStream_t s);
 hipError_t launch_tail(const Launch& L, hipStream_t s);
 hipError_t launch_finalize(const Launch& L, void* out_summaries, void* out_records,
                            uint64_t* out_exceptions, uint64_t exc_cap, hipStream_t s);
 hipError_t configure_kernels();
 int verify_occupancy(uint32_t block, size_t lds_bytes);
-size_t verify_static_lds();
+size_t verify_lds_bytes(const Launch& L);
+constexpr size_t kVerifyLdsMax = 159 * 1024;  // dynamic LDS per workgroup
 
 }  // namespace esq

@@ -2,7 +2,7 @@
 // point on any result and no matrix cores -- the sieve and the search are bit
 // operations over 64-bit words.
 //
-//   k_wheel_build  periodic pattern of odd multiples of 9, 25, 49, 121 (once)
+//   k_wheel_build  periodic pattern of odd multiples of 9, 25, 49 (once)
 //   k_prepare      zero the per-launch accumulators and the work queue
 //   k_bucket       primes above the medium range: every odd multiple of p^2
 //                  that falls in a segment region goes to that segment's hit
@@ -21,7 +21,8 @@ namespace esq {
 // ------------------------------------------------------------ wheel table
 
 // Word w holds bits for odd indices 64w .. 64w+63 (mod kWheelPeriod).  An odd
-// index x is an odd multiple of q = p^2 iff x = (q - 1)/2 (mod q).
+// index x is an odd multiple of q = p^2 iff x = (q - 1)/2 (mod q).  The word
+// pattern repeats every kWheelPeriod words since gcd(64, 9 * 25 * 49) = 1.
 __global__ void k_wheel_build(uint64_t* wheel, uint32_t nwords)
 {
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
@@ -30,12 +31,17 @@ __global__ void k_wheel_build(uint64_t* wheel, uint32_t nwords)
         uint64_t word = 0;
         for (uint32_t b = 0; b < 64; b++) {
             const uint32_t x = base + b;
-            if (x % 9u == 4u || x % 25u == 12u || x % 49u == 24u || x % 121u == 60u)
+            if (x % 9u == 4u || x % 25u == 12u || x % 49u == 24u)
                 word |= 1ull << b;
         }
         wheel[w] = word;
     }
 }
+
+// The odd multiples of 121 in word gw (odd indices 64 gw ...): at most one,
+// at bit j = (60 - 64 gw) mod 121 when j < 64.
+__device__ __forceinline__ uint64_t mask121(uint32_t j) { return j < 64 ? (1ull << j) : 0ull; }
+__device__ __forceinline__ uint32_t step121(uint32_t j, uint32_t d) { j += d; return j >= 121u ? j - 121u : j; }
 
 hipError_t launch_wheel_build(uint64_t* wheel, hipStream_t s)
 {
@@ -130,9 +136,15 @@ __device__ __forceinline__ void bucket_emit(const Launch& L, const Interval& iv,
     }
 }
 
-// grid.y = interval; threads [0, max_direct) take the bucket primes up to
-// kCofactorPrime one each, the following threads one odd cofactor j each.
-__global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t max_direct)
+// grid.y = interval.  Work units, in order: kHeavyPrimes-wide groups of
+// lanes for each of the first n_heavy bucket primes (many hits: the group
+// strides over them), then one thread per remaining bucket prime up to
+// kCofactorPrime, then kCofactorLanes lanes per odd cofactor j (primes above
+// kCofactorPrime, strided over the group).
+constexpr uint32_t kHeavyLanes = 64;
+constexpr uint32_t kCofactorLanes = 8;
+
+__global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint32_t max_direct)
 {
     const Interval iv = L.iv[blockIdx.y];
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,8 +153,21 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t max_direct)
     const uint64_t E = (uint64_t)(iv.nseg ? iv.nseg - 1 : 0) * S + (uint64_t)L.rw * 64;
     if (iv.nseg == 0)
         return;
-    if (t < max_direct) {
-        const uint64_t pi = L.med_end + t;
+    const uint64_t heavy_units = (uint64_t)n_heavy * kHeavyLanes;
+    if (t < heavy_units) {
+        const uint64_t pi = L.med_end + t / kHeavyLanes;
+        const uint32_t g = (uint32_t)(t % kHeavyLanes);
+        if (pi >= iv.b_direct_end)
+            return;
+        const uint64_t p = L.primes[pi];
+        const uint64_t q = p * p;
+        for (uint64_t y = first_hit(B0, q) + g * q; y < E; y += kHeavyLanes * q)
+            bucket_emit(L, iv, y);
+        return;
+    }
+    const uint64_t td = t - heavy_units;
+    if (td < max_direct) {
+        const uint64_t pi = L.med_end + n_heavy + td;
         if (pi >= iv.b_direct_end)
             return;
         const uint64_t p = L.primes[pi];
@@ -151,7 +176,9 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t max_direct)
             bucket_emit(L, iv, y);
         return;
     }
-    const uint64_t c = t - max_direct;
+    const uint64_t tc = td - max_direct;
+    const uint64_t c = tc / kCofactorLanes;
+    const uint32_t g = (uint32_t)(tc % kCofactorLanes);
     if (c >= iv.n_cof || iv.b_direct_end >= iv.pmax_end)
         return;
     // odd multiples j p^2 of the primes above kCofactorPrime, for one odd j
@@ -171,7 +198,7 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t max_direct)
         else
             hi = mid;
     }
-    for (uint32_t i = lo; i < iv.pmax_end; i++) {
+    for (uint32_t i = lo + g; i < iv.pmax_end; i += kCofactorLanes) {
         const uint64_t p = L.primes[i];
         if (p > pb)
             break;
@@ -182,13 +209,15 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t max_direct)
     }
 }
 
-hipError_t launch_bucket(const Launch& L, uint32_t max_direct, uint32_t max_cof, hipStream_t s)
+hipError_t launch_bucket(const Launch& L, uint32_t n_heavy, uint32_t max_direct, uint32_t max_cof,
+                         hipStream_t s)
 {
-    const uint64_t threads = (uint64_t)max_direct + max_cof;
+    const uint64_t threads =
+        (uint64_t)n_heavy * kHeavyLanes + max_direct + (uint64_t)max_cof * kCofactorLanes;
     if (threads == 0 || L.n_iv == 0)
         return hipSuccess;
     const uint32_t bx = (uint32_t)((threads + 255) / 256);
-    hipLaunchKernelGGL(k_bucket, dim3(bx, L.n_iv), dim3(256), 0, s, L, max_direct);
+    hipLaunchKernelGGL(k_bucket, dim3(bx, L.n_iv), dim3(256), 0, s, L, n_heavy, max_direct);
     return hipGetLastError();
 }
 
@@ -248,13 +277,17 @@ __device__ __forceinline__ void mark(uint32_t* bm32, uint32_t pos)
     atomicOr(&bm32[pos >> 5], 1u << (pos & 31));
 }
 
+// LDS layout of k_verify: the region bitmap (rw words), then the medium
+// primes' (q, S mod q), their current first-hit offsets, and -- when it fits
+// -- the lane-task table.
+__device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // MODE 0: verify, aggregates only; MODE 1: verify + per-n bytes;
 // MODE 2: Algorithm 1 alone, bitmap to HBM.
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_verify(Launch L)
 {
-    extern __shared__ uint64_t bm[];
-    __shared__ uint32_t s_f[kMaxMedium];
+    extern __shared__ uint64_t lds[];
     __shared__ unsigned long long s_first[kMaxKh + 2];
     __shared__ uint32_t s_cnt[kMaxKh + 1];
     __shared__ uint32_t s_item[4];
@@ -266,7 +299,20 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
     const uint32_t nmed = L.med_end - 4;
     const uint32_t klds = L.k_lds;
     const uint32_t wstep = SW % kWheelPeriod;
+    const uint32_t d121 = (121u - (64u * T) % 121u) % 121u;  // j121 change per T words
+    uint64_t* bm = lds;
     uint32_t* bm32 = reinterpret_cast<uint32_t*>(bm);
+    uint2* s_medq = reinterpret_cast<uint2*>(lds + L.rw);
+    uint32_t* s_f = reinterpret_cast<uint32_t*>(s_medq + nmed);
+    uint2* s_task = reinterpret_cast<uint2*>(lds + L.rw + nmed + (nmed + 1) / 2);
+    const uint2* tasks = L.tasks_in_lds ? s_task : L.tasks;
+
+    // per-launch tables into LDS (the bitmap region is rewritten per segment)
+    for (uint32_t i = tid; i < nmed; i += T)
+        s_medq[i] = L.medq[i];
+    if (L.tasks_in_lds)
+        for (uint32_t i = tid; i < L.n_tasks; i += T)
+            s_task[i] = L.tasks[i];
 
     for (;;) {
         if (tid == 0) {
@@ -295,9 +341,9 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
         if (tid <= kMaxKh)
             s_cnt[tid] = 0;
         __syncthreads();
-        if (!s_item[3])
+        if (!rfl(s_item[3]))
             break;
-        const uint32_t ivi = s_item[0], seg0 = s_item[1], nsegs = s_item[2];
+        const uint32_t ivi = rfl(s_item[0]), seg0 = rfl(s_item[1]), nsegs = rfl(s_item[2]);
         const Interval IV = L.iv[ivi];
         const uint32_t cap = L.bucket_cap;
 
@@ -305,36 +351,47 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
 #pragma unroll
         for (int k = 0; k <= kMaxKh; k++)
             cnt[k] = 0;
-        uint32_t found = 0;
+        uint32_t found = 0;  // levels whose least n this wave has already offered
 
         for (uint32_t seg = seg0; seg < seg0 + nsegs; seg++) {
             const int64_t Bs = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S;
             const int64_t gw0 = Bs / 64;  // exact: Bs is a multiple of 64
             const uint32_t wb = (uint32_t)(((uint64_t)IV.wheel_base0 + (uint64_t)seg * wstep) % kWheelPeriod);
 
-            // 1. the wheel pattern (words below odd index 0 are all marked);
-            //    each medium prime's first hit in the region
+            // 1. the wheel: odd multiples of 9, 25, 49 from the table, of 121 by
+            //    arithmetic (words below odd index 0 are all marked); each
+            //    medium prime's first hit in the region
             const uint64_t* src = L.wheel + wb;
+            int64_t g121 = (gw0 + (int64_t)tid) % 121;
+            if (g121 < 0)
+                g121 += 121;
+            uint32_t j121 = (uint32_t)((7804 - 64 * g121) % 121);  // 7804 = 60 + 64 * 121
             if (gw0 >= 0) {
                 uint32_t w = tid;
-                for (; w + 7 * T < L.rw; w += 8 * T) {
-                    uint64_t v[8];
+                for (; w + 3 * T < L.rw; w += 4 * T) {
+                    uint64_t v[4];
 #pragma unroll
-                    for (int u = 0; u < 8; u++)
+                    for (int u = 0; u < 4; u++)
                         v[u] = src[w + u * T];
 #pragma unroll
-                    for (int u = 0; u < 8; u++)
-                        bm[w + u * T] = v[u];
+                    for (int u = 0; u < 4; u++) {
+                        bm[w + u * T] = v[u] | mask121(j121);
+                        j121 = step121(j121, d121);
+                    }
                 }
-                for (; w < L.rw; w += T)
-                    bm[w] = src[w];
+                for (; w < L.rw; w += T) {
+                    bm[w] = src[w] | mask121(j121);
+                    j121 = step121(j121, d121);
+                }
             } else {
-                for (uint32_t w = tid; w < L.rw; w += T)
-                    bm[w] = (gw0 + (int64_t)w < 0) ? ~0ull : src[w];
+                for (uint32_t w = tid; w < L.rw; w += T) {
+                    bm[w] = (gw0 + (int64_t)w < 0) ? ~0ull : (src[w] | mask121(j121));
+                    j121 = step121(j121, d121);
+                }
             }
             if (seg == seg0) {
                 for (uint32_t i = tid; i < nmed; i += T) {
-                    const uint32_t q = L.medq[i].x;
+                    const uint32_t q = s_medq[i].x;
                     const int64_t d = (int64_t)((q - 1) >> 1) - Bs;
                     int64_t f = d % (int64_t)q;
                     if (f < 0)
@@ -343,7 +400,7 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                 }
             } else {
                 for (uint32_t i = tid; i < nmed; i += T) {
-                    const uint2 qs = L.medq[i];
+                    const uint2 qs = s_medq[i];
                     const uint32_t f = s_f[i];
                     s_f[i] = f >= qs.y ? f - qs.y : f + qs.x - qs.y;
                 }
@@ -353,12 +410,13 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
             // 2. odd multiples of p^2: medium primes by lane-tasks, larger ones
             //    from the segment's hit slots (directly if the slots overflowed)
             for (uint32_t e = tid; e < L.n_tasks; e += T) {
-                const MedTask tk = L.tasks[e];
-                const uint32_t v = tk.vc & 0xffffu, c = tk.vc >> 16;
-                const uint64_t p0 = (uint64_t)s_f[tk.idx] + (uint64_t)v * tk.q;
+                const uint2 tk = tasks[e];
+                const uint32_t idx = tk.x & 0xffffu, v = tk.x >> 16, c = tk.y;
+                const uint32_t q = s_medq[idx].x;
+                const uint64_t p0 = (uint64_t)s_f[idx] + (uint64_t)v * q;
                 if (p0 >= R)
                     continue;
-                const uint32_t step = c * tk.q;
+                const uint32_t step = c * q;
                 for (uint32_t pos = (uint32_t)p0; pos < R; pos += step)
                     mark(bm32, pos);
             }
@@ -405,54 +463,80 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                 continue;
             }
 
-            // 3. Algorithm 2, bit-sliced: U holds the n of one word still
-            //    without a representation; step k keeps the n whose n - 2^k
-            //    (2^(k-1) bits lower) is marked.  cnt[k] counts U after step k;
-            //    s_first[k+1] the least n in it.
+            // 3. Algorithm 2, bit-sliced: (uhi:ulo) holds the n of one word
+            //    still without a representation; step k keeps the n whose
+            //    n - 2^k (2^(k-1) bits lower) is marked.  cnt[k] counts them
+            //    after step k; s_first[k+1] collects the least such n.
             const uint64_t As = (uint64_t)(IV.A0 + (int64_t)seg * (int64_t)S);
             // main words wholly inside [I0, I1)
-            const uint64_t lo_w = IV.I0 > As ? (IV.I0 - As + 63) / 64 : 0;
-            const uint64_t hi_w = IV.I1 > As ? min((IV.I1 - As) / 64, (uint64_t)SW) : 0;
-            for (uint32_t mw = tid; mw < SW; mw += T) {
-                const uint32_t w = HW + mw;
+            uint32_t lo_w = 0, hi_w = SW;
+            if (IV.I0 > As)
+                lo_w = (uint32_t)min((IV.I0 - As + 63) / 64, (uint64_t)SW);
+            if (IV.I1 < As + S)
+                hi_w = IV.I1 > As ? (uint32_t)((IV.I1 - As) / 64) : 0u;
+            const bool all_valid = lo_w == 0 && hi_w == SW;
+            const uint32_t iters = (SW + T - 1) / T;
+            for (uint32_t itw = 0; itw < iters; itw++) {
+                const uint32_t mw = tid + itw * T;
+                const bool act = mw < SW;
+                const uint32_t w = HW + (act ? mw : 0u);
                 const uint64_t j0 = As + (uint64_t)mw * 64;
-                const uint64_t V = (mw >= lo_w && mw < hi_w) ? ~0ull : valid_mask(j0, IV.I0, IV.I1);
-                uint64_t U = V;
+                uint64_t V;
+                if (all_valid)
+                    V = act ? ~0ull : 0ull;
+                else
+                    V = !act ? 0ull
+                             : ((mw >= lo_w && mw < hi_w) ? ~0ull : valid_mask(j0, IV.I0, IV.I1));
                 const uint64_t cur = bm[w], prv = bm[w - 1];
+                const uint32_t clo = (uint32_t)cur, chi = (uint32_t)(cur >> 32);
+                const uint32_t plo = (uint32_t)prv, phi = (uint32_t)(prv >> 32);
+                uint32_t ulo = (uint32_t)V, uhi = (uint32_t)(V >> 32);
                 uint32_t D[16];
                 if (MODE == 1) {
 #pragma unroll
                     for (int i = 0; i < 16; i++)
                         D[i] = spread4((uint32_t)(V >> (4 * i)) & 15u);
                 }
+                found = rfl(found);
 #pragma unroll
                 for (int k = 1; k <= kMaxKh; k++) {
                     if (k > (int)klds)
                         break;
-                    uint64_t win;
-                    if (k <= 6) {
-                        const int sh = 1 << (k - 1);
-                        win = (cur << sh) | (prv >> (64 - sh));
+                    uint32_t wlo, whi;
+                    if (k <= 5) {
+                        const uint32_t sh = 32u - (1u << (k - 1));
+                        wlo = __builtin_amdgcn_alignbit(clo, phi, sh);
+                        whi = __builtin_amdgcn_alignbit(chi, clo, sh);
+                    } else if (k == 6) {
+                        wlo = phi;
+                        whi = clo;
                     } else if (k == 7) {
-                        win = prv;
+                        wlo = plo;
+                        whi = phi;
                     } else {
-                        win = U ? bm[w - (1u << (k - 7))] : 0ull;
+                        const uint64_t x = (ulo | uhi) ? bm[w - (1u << (k - 7))] : 0ull;
+                        wlo = (uint32_t)x;
+                        whi = (uint32_t)(x >> 32);
                     }
-                    U &= win;
-                    cnt[k] += (uint32_t)__popcll(U);
+                    ulo &= wlo;
+                    uhi &= whi;
+                    cnt[k] += __popc(ulo);
+                    cnt[k] += __popc(uhi);
                     if (MODE == 1) {
+                        const uint64_t U = ((uint64_t)uhi << 32) | ulo;
 #pragma unroll
                         for (int i = 0; i < 16; i++)
                             D[i] += spread4((uint32_t)(U >> (4 * i)) & 15u);
                     }
                     const bool track = !(found & (1u << (k + 1)));
                     if (k >= 3 || track) {
-                        const uint64_t b = __ballot(U != 0);
+                        const uint64_t b = __ballot((ulo | uhi) != 0);
                         if (b == 0)
                             break;
                         if (track) {
-                            const int l = __ffsll((unsigned long long)b) - 1;
-                            if (lane == (uint32_t)l) {
+                            const uint32_t l = rfl((uint32_t)(__ffsll((unsigned long long)b) - 1));
+                            if (lane == l) {
+                                const uint64_t U = ((uint64_t)uhi << 32) | ulo;
                                 const uint64_t n_first = j0 + (uint64_t)(__ffsll((unsigned long long)U) - 1);
                                 atomicMin(&s_first[k + 1], (unsigned long long)n_first);
                             }
@@ -460,6 +544,7 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                         }
                     }
                 }
+                const uint64_t U = ((uint64_t)uhi << 32) | ulo;
                 if (U) {
                     // still unresolved after the in-LDS steps: exact tail pass
                     uint64_t x = U;
@@ -510,9 +595,16 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
     }
 }
 
+size_t verify_lds_bytes(const Launch& L)
+{
+    const size_t nmed = L.med_end - 4;
+    return (size_t)L.rw * 8 + nmed * 8 + ((nmed + 1) / 2) * 8 +
+           (L.tasks_in_lds ? (size_t)L.n_tasks * 8 : 0);
+}
+
 hipError_t launch_verify(const Launch& L, uint32_t grid, uint32_t block, hipStream_t s)
 {
-    const size_t lds = (size_t)L.rw * 8;
+    const size_t lds = verify_lds_bytes(L);
     if (grid == 0 || L.n_items == 0)
         return hipSuccess;
     switch (L.mode) {
@@ -538,11 +630,6 @@ int verify_occupancy(uint32_t block, size_t lds_bytes)
     return occ > 0 ? occ : 1;
 }
 
-size_t verify_static_lds()
-{
-    return sizeof(uint32_t) * kMaxMedium + sizeof(unsigned long long) * (kMaxKh + 2) +
-           sizeof(uint32_t) * (kMaxKh + 1) + 16;
-}
 
 // --------------------------------------------------------------- tail
 
@@ -698,21 +785,22 @@ __global__ __launch_bounds__(1024) void k_finalize(Launch L, void* out_summaries
     }
     __syncthreads();
 
+    __shared__ unsigned long long h[65];
+    __shared__ unsigned long long s_cnt[16];
+    for (uint32_t i = tid; i < 65; i += T)
+        h[i] = A->deep_hist[i];
+    for (uint32_t i = tid; i < 16; i += T)
+        s_cnt[i] = A->cnt[i];
+    __syncthreads();
     if (tid != 0)
         return;
     esq_summary* out = reinterpret_cast<esq_summary*>(out_summaries) + ivi;
-    unsigned long long h[65];
-    for (int k = 0; k < 65; k++)
-        h[k] = 0;
     unsigned long long prev = n_odd;
     for (uint32_t k = 1; k <= L.k_lds; k++) {
-        const unsigned long long c = A->cnt[k];
-        h[k] = prev - c;
+        const unsigned long long c = s_cnt[k];
+        h[k] = prev - c;   // the tail pass only fills depths above k_lds
         prev = c;
     }
-    for (uint32_t k = L.k_lds + 1; k < 65; k++)
-        h[k] += A->deep_hist[k];
-    h[0] = A->deep_hist[0];
     unsigned long long ksum = 0;
     uint32_t kseen = 0;
     for (uint32_t k = 1; k < 65; k++) {
@@ -769,7 +857,7 @@ hipError_t launch_finalize(const Launch& L, void* out_summaries, void* out_recor
 hipError_t configure_kernels()
 {
     hipError_t e;
-    const int lds_max = 160 * 1024 - (int)verify_static_lds() - 1024;
+    const int lds_max = (int)kVerifyLdsMax;
     e = hipFuncSetAttribute((const void*)k_verify<0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_verify<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);

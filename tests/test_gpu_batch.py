@@ -9,8 +9,8 @@ import oracle
 from paper_2411_01964_amd import esq, workloads
 
 pytestmark = pytest.mark.gpu
-DEFAULTS = dict(seg_log2=18, kh=13, block=256, entry_hits=16, tail_cap=1 << 20,
-                medium_max=8191, bucket_cap=0, items_per_wg=4)
+DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
+                medium_max=4095, bucket_cap=0, items_per_wg=4)
 
 
 @pytest.fixture(scope="module", autouse=True)

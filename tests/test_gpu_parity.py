@@ -13,7 +13,8 @@ from tests.conftest import read_golden
 pytestmark = pytest.mark.gpu
 
 MAX_HI = (1 << 50) + (1 << 33)
-DEFAULTS = dict(seg_log2=18, kh=13, block=256, entry_hits=16, tail_cap=1 << 20)
+DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
+                medium_max=4095, bucket_cap=0, items_per_wg=4)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -90,6 +91,8 @@ def test_config1_full_exact():
     dict(seg_log2=10), dict(seg_log2=12, block=64), dict(seg_log2=20, block=1024),
     dict(kh=1), dict(kh=2), dict(kh=4), dict(kh=6), dict(kh=7), dict(kh=8),
     dict(entry_hits=1), dict(entry_hits=4096), dict(seg_log2=11, kh=9, block=128),
+    dict(medium_max=11), dict(medium_max=11000), dict(medium_max=101, bucket_cap=1),
+    dict(block=256, medium_max=8191), dict(seg_log2=16, block=128),
 ])
 def test_knob_invariance(kw):
     knobs(**kw)
