@@ -39,6 +39,28 @@ LDS_BYTES_PER_N = 0.125 + 4 * 0.02241 + 0.125
 VALU_OPS_PER_N = 6 * 2.928 / 64
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2411_01964_amd", "csrc", "esq_kernels.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_verify_cfg3.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the segment kernel from the rocprofv3 counter
+    runs recorded in profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by the
+    copy-probe factors) -- only while the kernel source is the one measured."""
+    import hashlib
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != sha:
+        return None
+    return (t["fetch_kib_per_launch"] * t["fetch_factor"] +
+            t["write_kib_per_launch"] * t["write_factor"]) * 1024.0
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -219,6 +241,9 @@ def main():
                 "unit": "GB/s", "frac": lds_ach / LDS_PEAK, "traffic": None,
                 "kernel": "k_segment", "kernel_ms": seg_avg_s * 1e3}
     roof, alt = (roof_valu, roof_lds) if roof_valu["frac"] >= roof_lds["frac"] else (roof_lds, roof_valu)
+    traffic = measured_traffic() if args.workload == "cfg3_near_2pow50" else None
+    roof["traffic"] = traffic
+    alt["traffic"] = traffic
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -62,7 +62,9 @@ struct Ctx {
     std::vector<double> inv_pref;   // inv_pref[i] = sum over t < i of 1 / primes[t]^2
     uint32_t* d_primes = nullptr;
     uint64_t* d_wheel = nullptr;
+    uint64_t* d_wheel2 = nullptr;
     std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
+    std::map<std::pair<uint32_t, size_t>, int> occupancy;  // (block, LDS bytes) -> workgroups per CU
 };
 
 std::mutex g_mu;
@@ -217,6 +219,8 @@ void free_ctx(Ctx* c)
         (void)hipFree(c->d_primes);
     if (c->d_wheel)
         (void)hipFree(c->d_wheel);
+    if (c->d_wheel2)
+        (void)hipFree(c->d_wheel2);
     delete c;
 }
 
@@ -229,7 +233,7 @@ uint32_t prime_upper(const Ctx* c, uint64_t x)
                       c->primes.begin());
 }
 
-// Medium primes primes[4 .. med_end) for a region of rw words and segment
+// Medium primes primes[kFirstMedium .. med_end) for a region of rw words and segment
 // length S: per prime (q, S mod q), and lane-tasks -- prime i with up to
 // h = ceil(R / q) marks per region is split into c = ceil(h / entry_hits)
 // tasks; task v marks f + (v + c t) q, t >= 0.
@@ -245,11 +249,11 @@ int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_
     }
     const uint64_t R = (uint64_t)rw * 64;
     const uint64_t S = 1ull << log2S;
-    const uint32_t nmed = med_end - 4;
+    const uint32_t nmed = med_end - kFirstMedium;
     std::vector<std::pair<uint64_t, uint2>> tasks;
     std::vector<uint2> medq(std::max<uint32_t>(nmed, 1));
     for (uint32_t i = 0; i < nmed; i++) {
-        const uint64_t p = c->primes[4 + i];
+        const uint64_t p = c->primes[kFirstMedium + i];
         const uint64_t q = p * p;
         medq[i].x = (uint32_t)q;
         medq[i].y = (uint32_t)(S % q);
@@ -398,10 +402,10 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
         pmax_all = std::max(pmax_all, pmax[i]);
     }
 
-    // medium primes: 13 .. min(medium_max, largest needed)
-    uint32_t med_end = std::max<uint32_t>(4, prime_upper(c, std::min<uint64_t>(
+    // medium primes: 17 .. min(medium_max, largest needed)
+    uint32_t med_end = std::max<uint32_t>(kFirstMedium, prime_upper(c, std::min<uint64_t>(
                                                   (uint64_t)par.medium_max, pmax_all)));
-    med_end = std::min<uint32_t>(med_end, 4 + (uint32_t)kMaxMedium);
+    med_end = std::min<uint32_t>(med_end, kFirstMedium + (uint32_t)kMaxMedium);
     const uint32_t direct_end = prime_upper(c, kCofactorPrime);
     uint32_t max_direct = 0, max_cof = 0;
     bool any_bucket = false;
@@ -438,7 +442,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
 
     MedTable* mt = nullptr;
     int rc;
-    if (med_end > 4 && (rc = get_med_table(c, rw, log2S, med_end, (uint32_t)par.entry_hits, &mt)))
+    if (med_end > kFirstMedium && (rc = get_med_table(c, rw, log2S, med_end, (uint32_t)par.entry_hits, &mt)))
         return rc;
 
     uint32_t cap = 0;
@@ -453,7 +457,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     }
 
     // LDS of the segment kernel: bitmap + medium-prime tables (+ tasks if they fit)
-    const size_t nmed = med_end - 4;
+    const size_t nmed = med_end - kFirstMedium;
     const size_t lds_base = (size_t)rw * 8 + nmed * 8 + ((nmed + 1) / 2) * 8;
     if (lds_base > kVerifyLdsMax)
         return fail(ESQ_EINVAL, "segment too large for LDS with these medium primes");
@@ -462,7 +466,15 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     const size_t lds_bytes = lds_base + (tasks_in_lds ? (size_t)n_tasks * 8 : 0);
 
     // work items: runs of consecutive segments
-    const int occ = verify_occupancy((uint32_t)par.block, lds_bytes);
+    int occ;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        const auto key = std::make_pair((uint32_t)par.block, lds_bytes);
+        auto it = c->occupancy.find(key);
+        if (it == c->occupancy.end())
+            it = c->occupancy.emplace(key, verify_occupancy((uint32_t)par.block, lds_bytes)).first;
+        occ = it->second;
+    }
     const uint64_t resident = (uint64_t)c->n_cu * (uint64_t)occ;
     std::vector<uint4>& items = P->items;
     items.clear();
@@ -527,6 +539,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.medq = mt ? mt->medq : nullptr;
     L.tasks = mt ? mt->tasks : nullptr;
     L.wheel = c->d_wheel;
+    L.wheel2 = c->d_wheel2;
     L.tail_cap = tail_cap;
     P->mode = mode;
     P->n_heavy = n_heavy;
@@ -695,12 +708,14 @@ int esq_init(int device, uint64_t max_hi)
             return hip_fail(e, "hipFuncSetAttribute");
         }
         e = hipMalloc(&g_ctx->d_wheel, (size_t)(kWheelPeriod + kWheelExtra) * 8);
+        if (e == hipSuccess)
+            e = hipMalloc(&g_ctx->d_wheel2, (size_t)(kWheel2Period + kWheelExtra) * 8);
         if (e != hipSuccess) {
             free_ctx(g_ctx);
             g_ctx = nullptr;
             return fail(ESQ_ENOMEM, "hipMalloc(wheel)");
         }
-        if ((e = launch_wheel_build(g_ctx->d_wheel, nullptr)) != hipSuccess) {
+        if ((e = launch_wheel_build(g_ctx->d_wheel, g_ctx->d_wheel2, nullptr)) != hipSuccess) {
             free_ctx(g_ctx);
             g_ctx = nullptr;
             return hip_fail(e, "k_wheel_build");

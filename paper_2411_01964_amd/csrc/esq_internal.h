@@ -24,6 +24,8 @@ namespace esq {
 
 constexpr uint32_t kWheelPeriod = 9u * 25u * 49u;  // 11025 words: the table stays in L2
 constexpr uint32_t kWheelExtra = 16640;   // >= largest region in 64-bit words
+constexpr uint32_t kWheel2Period = 121u * 169u;  // 20449 words: second table (11^2, 13^2)
+constexpr uint32_t kFirstMedium = 5;      // primes[0 .. 5) = 3, 5, 7, 11, 13: the two tables
 constexpr int kMaxKh = 13;                // deepest in-LDS level supported
 constexpr int kMaxMedium = 1536;          // medium primes per launch (LDS offsets)
 constexpr unsigned long long kNone = ~0ull;
@@ -60,7 +62,7 @@ struct Interval {
 };
 
 // Medium-prime lane-task, packed in a uint2: x = idx | (v << 16), y = c;
-// it marks f + (v + c t) q, t >= 0, of medium prime idx (0 = the prime 13).
+// it marks f + (v + c t) q, t >= 0, of medium prime idx (0 = the prime 17).
 
 // Geometry and resources shared by every interval of a launch.
 struct Launch {
@@ -70,7 +72,7 @@ struct Launch {
     uint32_t n_items;             // work items in the queue
     uint32_t run;                 // single interval: segments per item (0 = use items[])
     uint32_t mode;                // 0 verify, 1 verify + per-n, 2 sieve
-    uint32_t med_end;             // medium primes primes[4 .. med_end)
+    uint32_t med_end;             // medium primes primes[kFirstMedium .. med_end)
     uint32_t n_tasks;
     uint32_t k_lds, kmax_eff;
     uint32_t bucket_cap;          // hit slots per segment
@@ -81,7 +83,8 @@ struct Launch {
     const uint2* medq;            // per medium prime: (q, S mod q)
     const uint2* tasks;           // medium-prime lane-tasks
     uint32_t tasks_in_lds;        // 1: the task table is copied into LDS
-    const uint64_t* wheel;        // kWheelPeriod + kWheelExtra words
+    const uint64_t* wheel;        // kWheelPeriod + kWheelExtra words (9, 25, 49)
+    const uint64_t* wheel2;       // kWheel2Period + kWheelExtra words (121, 169)
     uint32_t* bucket_cnt;         // per global segment
     uint32_t* bucket_slot;        // bucket_cap per global segment
     unsigned int* queue;          // work-queue head
@@ -93,7 +96,7 @@ struct Launch {
 };
 
 // launchers (esq_kernels.hip); all return hipError_t of the launch
-hipError_t launch_wheel_build(uint64_t* wheel, hipStream_t s);
+hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, hipStream_t s);
 hipError_t launch_prepare(const Launch& L, Acc* accs, const Interval* iv_single,
                           uint32_t nseg_total, hipStream_t s);
 hipError_t launch_bucket(const Launch& L, uint32_t n_heavy, uint32_t max_direct, uint32_t max_cof,

@@ -2,7 +2,7 @@
 // point on any result and no matrix cores -- the sieve and the search are bit
 // operations over 64-bit words.
 //
-//   k_wheel_build  periodic pattern of odd multiples of 9, 25, 49 (once)
+//   k_wheel_build  periodic patterns of odd multiples of 9, 25, 49 and of 121, 169 (once)
 //   k_prepare      zero the per-launch accumulators and the work queue
 //   k_bucket       primes above the medium range: every odd multiple of p^2
 //                  that falls in a segment region goes to that segment's hit
@@ -13,6 +13,8 @@
 //                  bitmap streamed to HBM)
 //   k_tail         exact search for the rare n not resolved from LDS
 //   k_finalize     per interval: aggregates, record-setters, exceptions
+#include <type_traits>
+
 #include "esq.h"
 #include "esq_internal.h"
 
@@ -20,34 +22,48 @@ namespace esq {
 
 // ------------------------------------------------------------ wheel table
 
-// Word w holds bits for odd indices 64w .. 64w+63 (mod kWheelPeriod).  An odd
-// index x is an odd multiple of q = p^2 iff x = (q - 1)/2 (mod q).  The word
-// pattern repeats every kWheelPeriod words since gcd(64, 9 * 25 * 49) = 1.
-__global__ void k_wheel_build(uint64_t* wheel, uint32_t nwords)
+// Word w holds bits for odd indices 64w .. 64w+63 (mod the period).  An odd
+// index x is an odd multiple of q = p^2 iff x = (q - 1)/2 (mod q).  A word
+// pattern repeats every `period` words when gcd(64, period) = 1: 9 * 25 * 49
+// for the first table, 121 * 169 for the second.  Both tables carry
+// kWheelExtra more words so that a region never wraps; together they take
+// about 0.5 MB and stay in L2.
+__global__ void k_wheel_build(uint64_t* wheel, uint64_t* wheel2)
 {
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
+    const uint32_t n1 = kWheelPeriod + kWheelExtra, n2 = kWheel2Period + kWheelExtra;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < n1 + n2;
          w += gridDim.x * blockDim.x) {
-        const uint32_t base = (uint32_t)(((uint64_t)w * 64u) % kWheelPeriod);
+        const bool second = w >= n1;
+        const uint32_t ww = second ? w - n1 : w;
+        const uint32_t period = second ? kWheel2Period : kWheelPeriod;
+        const uint32_t base = (uint32_t)(((uint64_t)ww * 64u) % period);
         uint64_t word = 0;
         for (uint32_t b = 0; b < 64; b++) {
             const uint32_t x = base + b;
-            if (x % 9u == 4u || x % 25u == 12u || x % 49u == 24u)
+            const bool hit = second ? (x % 121u == 60u || x % 169u == 84u)
+                                    : (x % 9u == 4u || x % 25u == 12u || x % 49u == 24u);
+            if (hit)
                 word |= 1ull << b;
         }
-        wheel[w] = word;
+        if (second)
+            wheel2[ww] = word;
+        else
+            wheel[ww] = word;
     }
 }
 
-// The odd multiples of 121 in word gw (odd indices 64 gw ...): at most one,
-// at bit j = (60 - 64 gw) mod 121 when j < 64.
-__device__ __forceinline__ uint64_t mask121(uint32_t j) { return j < 64 ? (1ull << j) : 0ull; }
-__device__ __forceinline__ uint32_t step121(uint32_t j, uint32_t d) { j += d; return j >= 121u ? j - 121u : j; }
-
-hipError_t launch_wheel_build(uint64_t* wheel, hipStream_t s)
+hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_wheel_build, dim3(1024), dim3(256), 0, s, wheel,
-                       kWheelPeriod + kWheelExtra);
+    hipLaunchKernelGGL(k_wheel_build, dim3(1024), dim3(256), 0, s, wheel, wheel2);
     return hipGetLastError();
+}
+
+// popcount(x) + acc in one v_bcnt_u32_b32
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
 }
 
 // --------------------------------------------------------------- prepare
@@ -285,7 +301,7 @@ __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_re
 // MODE 0: verify, aggregates only; MODE 1: verify + per-n bytes;
 // MODE 2: Algorithm 1 alone, bitmap to HBM.
 template <int MODE>
-__global__ __launch_bounds__(1024) void k_verify(Launch L)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 4 : 6))) void k_verify(Launch L)
 {
     extern __shared__ uint64_t lds[];
     __shared__ unsigned long long s_first[kMaxKh + 2];
@@ -296,10 +312,9 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
     const uint32_t S = 1u << L.log2S, SW = S >> 6;
     const uint32_t R = L.rw * 64;
     const uint32_t HW = L.hlo_words;
-    const uint32_t nmed = L.med_end - 4;
+    const uint32_t nmed = L.med_end - kFirstMedium;
     const uint32_t klds = L.k_lds;
     const uint32_t wstep = SW % kWheelPeriod;
-    const uint32_t d121 = (121u - (64u * T) % 121u) % 121u;  // j121 change per T words
     uint64_t* bm = lds;
     uint32_t* bm32 = reinterpret_cast<uint32_t*>(bm);
     uint2* s_medq = reinterpret_cast<uint2*>(lds + L.rw);
@@ -347,9 +362,12 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
         const Interval IV = L.iv[ivi];
         const uint32_t cap = L.bucket_cap;
 
-        uint32_t cnt[kMaxKh + 1];
+        // per-lane counts of levels 1 .. kRegLevels; deeper levels, reached by
+        // few words, count straight into s_cnt
+        constexpr int kRegLevels = 4;
+        uint32_t cnt[kRegLevels + 1];
 #pragma unroll
-        for (int k = 0; k <= kMaxKh; k++)
+        for (int k = 0; k <= kRegLevels; k++)
             cnt[k] = 0;
         uint32_t found = 0;  // levels whose least n this wave has already offered
 
@@ -358,36 +376,41 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
             const int64_t gw0 = Bs / 64;  // exact: Bs is a multiple of 64
             const uint32_t wb = (uint32_t)(((uint64_t)IV.wheel_base0 + (uint64_t)seg * wstep) % kWheelPeriod);
 
-            // 1. the wheel: odd multiples of 9, 25, 49 from the table, of 121 by
-            //    arithmetic (words below odd index 0 are all marked); each
-            //    medium prime's first hit in the region
-            const uint64_t* src = L.wheel + wb;
-            int64_t g121 = (gw0 + (int64_t)tid) % 121;
-            if (g121 < 0)
-                g121 += 121;
-            uint32_t j121 = (uint32_t)((7804 - 64 * g121) % 121);  // 7804 = 60 + 64 * 121
+            // 1. the wheel: odd multiples of 9, 25, 49 and of 121, 169 from the
+            //    two tables (words below odd index 0 are all marked); each
+            //    medium prime's first hit in the region.  Byte offsets are
+            //    32-bit so that a load is a scalar base plus one lane offset.
+            int64_t g2 = gw0 % (int64_t)kWheel2Period;
+            if (g2 < 0)
+                g2 += kWheel2Period;
+            const char* src = reinterpret_cast<const char*>(L.wheel + wb);
+            const char* src2 = reinterpret_cast<const char*>(L.wheel2 + g2);
+            char* dst = reinterpret_cast<char*>(bm);
             if (gw0 >= 0) {
-                uint32_t w = tid;
-                for (; w + 3 * T < L.rw; w += 4 * T) {
-                    uint64_t v[4];
-#pragma unroll
-                    for (int u = 0; u < 4; u++)
-                        v[u] = src[w + u * T];
+                const uint32_t passes = L.rw / (4 * T);
+                const uint32_t st = 8 * T;
+                uint32_t off = 8 * tid;
+                for (uint32_t ps = 0; ps < passes; ps++, off += 4 * st) {
+                    uint64_t v[4], x[4];
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
-                        bm[w + u * T] = v[u] | mask121(j121);
-                        j121 = step121(j121, d121);
+                        v[u] = *reinterpret_cast<const uint64_t*>(src + off + u * st);
+                        x[u] = *reinterpret_cast<const uint64_t*>(src2 + off + u * st);
                     }
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        *reinterpret_cast<uint64_t*>(dst + off + u * st) = v[u] | x[u];
                 }
-                for (; w < L.rw; w += T) {
-                    bm[w] = src[w] | mask121(j121);
-                    j121 = step121(j121, d121);
-                }
+                for (; off < 8 * L.rw; off += st)
+                    *reinterpret_cast<uint64_t*>(dst + off) =
+                        *reinterpret_cast<const uint64_t*>(src + off) |
+                        *reinterpret_cast<const uint64_t*>(src2 + off);
             } else {
-                for (uint32_t w = tid; w < L.rw; w += T) {
-                    bm[w] = (gw0 + (int64_t)w < 0) ? ~0ull : (src[w] | mask121(j121));
-                    j121 = step121(j121, d121);
-                }
+                for (uint32_t w = tid; w < L.rw; w += T)
+                    bm[w] = (gw0 + (int64_t)w < 0)
+                                ? ~0ull
+                                : (reinterpret_cast<const uint64_t*>(src)[w] |
+                                   reinterpret_cast<const uint64_t*>(src2)[w]);
             }
             if (seg == seg0) {
                 for (uint32_t i = tid; i < nmed; i += T) {
@@ -474,19 +497,29 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                 lo_w = (uint32_t)min((IV.I0 - As + 63) / 64, (uint64_t)SW);
             if (IV.I1 < As + S)
                 hi_w = IV.I1 > As ? (uint32_t)((IV.I1 - As) / 64) : 0u;
-            const bool all_valid = lo_w == 0 && hi_w == SW;
+            // A segment whose main words all lie inside [I0, I1) and split
+            // evenly over the workgroup, searched to the deepest in-LDS level,
+            // takes the fast form: every lane active, every n valid, no
+            // per-word index arithmetic, no level bound.
+            const bool fast = MODE == 0 && lo_w == 0 && hi_w == SW && SW % T == 0 && klds == (uint32_t)kMaxKh;
             const uint32_t iters = (SW + T - 1) / T;
-            for (uint32_t itw = 0; itw < iters; itw++) {
+            // STEADY: the least n of depth 2 .. 5 have been offered already, so
+            // steps 1 .. 4 run without any branch.
+            auto word_pass = [&](auto fast_c, auto steady_c, uint32_t itw) {
+                constexpr bool FAST = decltype(fast_c)::value;
+                constexpr bool STEADY = decltype(steady_c)::value;
                 const uint32_t mw = tid + itw * T;
-                const bool act = mw < SW;
+                const bool act = FAST || mw < SW;
                 const uint32_t w = HW + (act ? mw : 0u);
-                const uint64_t j0 = As + (uint64_t)mw * 64;
                 uint64_t V;
-                if (all_valid)
-                    V = act ? ~0ull : 0ull;
+                if (FAST)
+                    V = ~0ull;
+                else if (!act)
+                    V = 0;
+                else if (mw >= lo_w && mw < hi_w)
+                    V = ~0ull;
                 else
-                    V = !act ? 0ull
-                             : ((mw >= lo_w && mw < hi_w) ? ~0ull : valid_mask(j0, IV.I0, IV.I1));
+                    V = valid_mask(As + (uint64_t)mw * 64, IV.I0, IV.I1);
                 const uint64_t cur = bm[w], prv = bm[w - 1];
                 const uint32_t clo = (uint32_t)cur, chi = (uint32_t)(cur >> 32);
                 const uint32_t plo = (uint32_t)prv, phi = (uint32_t)(prv >> 32);
@@ -498,9 +531,10 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                         D[i] = spread4((uint32_t)(V >> (4 * i)) & 15u);
                 }
                 found = rfl(found);
+                bool alive = true;  // wave-uniform: some lane still has an n left
 #pragma unroll
                 for (int k = 1; k <= kMaxKh; k++) {
-                    if (k > (int)klds)
+                    if (!FAST && k > (int)klds)
                         break;
                     uint32_t wlo, whi;
                     if (k <= 5) {
@@ -520,24 +554,31 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                     }
                     ulo &= wlo;
                     uhi &= whi;
-                    cnt[k] += __popc(ulo);
-                    cnt[k] += __popc(uhi);
+                    if (k <= kRegLevels)
+                        cnt[k] = bcnt_acc(uhi, bcnt_acc(ulo, cnt[k]));
+                    else if (ulo | uhi)
+                        atomicAdd(&s_cnt[k], (uint32_t)(__popc(ulo) + __popc(uhi)));
                     if (MODE == 1) {
                         const uint64_t U = ((uint64_t)uhi << 32) | ulo;
 #pragma unroll
                         for (int i = 0; i < 16; i++)
                             D[i] += spread4((uint32_t)(U >> (4 * i)) & 15u);
                     }
-                    const bool track = !(found & (1u << (k + 1)));
-                    if (k >= 3 || track) {
-                        const uint64_t b = __ballot((ulo | uhi) != 0);
-                        if (b == 0)
+                    // a wave of 4096 n almost never empties before step 4, so
+                    // the test for an empty wave starts there
+                    const bool track = !(STEADY && k <= 4) && !(found & (1u << (k + 1)));
+                    if (k >= 4 || track) {
+                        const uint64_t bal = __ballot((ulo | uhi) != 0);
+                        if (bal == 0) {
+                            alive = false;
                             break;
+                        }
                         if (track) {
-                            const uint32_t l = rfl((uint32_t)(__ffsll((unsigned long long)b) - 1));
+                            const uint32_t l = rfl((uint32_t)(__ffsll((unsigned long long)bal) - 1));
                             if (lane == l) {
                                 const uint64_t U = ((uint64_t)uhi << 32) | ulo;
-                                const uint64_t n_first = j0 + (uint64_t)(__ffsll((unsigned long long)U) - 1);
+                                const uint64_t n_first = As + (uint64_t)mw * 64 +
+                                                         (uint64_t)(__ffsll((unsigned long long)U) - 1);
                                 atomicMin(&s_first[k + 1], (unsigned long long)n_first);
                             }
                             found |= 1u << (k + 1);
@@ -545,8 +586,9 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                     }
                 }
                 const uint64_t U = ((uint64_t)uhi << 32) | ulo;
-                if (U) {
+                if (alive && U) {
                     // still unresolved after the in-LDS steps: exact tail pass
+                    const uint64_t j0 = As + (uint64_t)mw * 64;
                     uint64_t x = U;
                     atomicAdd(&IV.acc->tail_count, (unsigned long long)__popcll(U));
                     while (x) {
@@ -562,6 +604,7 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                     }
                 }
                 if (MODE == 1 && V && IV.out_mink) {
+                    const uint64_t j0 = As + (uint64_t)mw * 64;
                     if (U) {
 #pragma unroll
                         for (int i = 0; i < 16; i++)
@@ -569,6 +612,15 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
                     }
                     store_depths(IV.out_mink + ((int64_t)j0 - (int64_t)IV.I0), D, V);
                 }
+            };
+            constexpr uint32_t kSteadyBits = 0x3Cu;  // levels 2 .. 5
+            for (uint32_t itw = 0; itw < iters; itw++) {
+                if (!fast)
+                    word_pass(std::false_type{}, std::false_type{}, itw);
+                else if ((rfl(found) & kSteadyBits) == kSteadyBits)
+                    word_pass(std::true_type{}, std::true_type{}, itw);
+                else
+                    word_pass(std::true_type{}, std::false_type{}, itw);
             }
             __syncthreads();
         }
@@ -576,7 +628,7 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
         // 4. the item's totals -> the interval's accumulators
         if (MODE != 2) {
 #pragma unroll
-            for (int k = 1; k <= kMaxKh; k++) {
+            for (int k = 1; k <= kRegLevels; k++) {
                 if (k > (int)klds)
                     break;
                 uint32_t v = cnt[k];
@@ -597,7 +649,7 @@ __global__ __launch_bounds__(1024) void k_verify(Launch L)
 
 size_t verify_lds_bytes(const Launch& L)
 {
-    const size_t nmed = L.med_end - 4;
+    const size_t nmed = L.med_end - kFirstMedium;
     return (size_t)L.rw * 8 + nmed * 8 + ((nmed + 1) / 2) * 8 +
            (L.tasks_in_lds ? (size_t)L.n_tasks * 8 : 0);
 }

@@ -51,6 +51,19 @@ SUMMARY_BYTES = ctypes.sizeof(Summary)
 RECORD_BYTES = ctypes.sizeof(Record)
 
 
+def _np_dtypes():
+    import numpy as np
+    summary = np.dtype([("n0", "<u8"), ("n_odd", "<u8"), ("hist", "<u8", 65), ("ksum", "<u8"),
+                        ("kmax_seen", "<u4"), ("n_records", "<u4"), ("n_exceptions", "<u8"),
+                        ("status", "<u4"), ("reserved", "<u4")])
+    record = np.dtype([("n", "<u8"), ("k", "<u4"), ("reserved", "<u4")])
+    assert summary.itemsize == SUMMARY_BYTES and record.itemsize == RECORD_BYTES
+    return summary, record
+
+
+SUMMARY_DTYPE, RECORD_DTYPE = _np_dtypes()
+
+
 class EsqError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("libesq error %d: %s" % (code, msg))
@@ -245,6 +258,28 @@ def _parse(summary_bytes, record_bytes):
     }
 
 
+def _parse_many(summaries, records, count):
+    """Summaries and records of count intervals from their device buffers."""
+    sm = summaries[:count * SUMMARY_BYTES].cpu().numpy().view(SUMMARY_DTYPE)
+    rc = records[:count * ESQ_RECORDS_CAP * RECORD_BYTES].cpu().numpy().view(RECORD_DTYPE)
+    rc = rc.reshape(count, ESQ_RECORDS_CAP)
+    hist = sm["hist"].tolist()
+    cols = {k: sm[k].tolist() for k in ("n0", "n_odd", "ksum", "kmax_seen", "n_records",
+                                         "n_exceptions", "status")}
+    rn, rk = rc["n"].tolist(), rc["k"].tolist()
+    out = []
+    for i in range(count):
+        nrec = min(cols["n_records"][i], ESQ_RECORDS_CAP)
+        out.append({
+            "n0": cols["n0"][i], "n_odd": cols["n_odd"][i], "hist": hist[i],
+            "ksum": cols["ksum"][i], "kmax_seen": cols["kmax_seen"][i],
+            "n_records": cols["n_records"][i],
+            "records": list(zip(rn[i][:nrec], rk[i][:nrec])),
+            "n_exceptions": cols["n_exceptions"][i], "status": cols["status"][i],
+        })
+    return out
+
+
 class PendingBatch:
     """Device buffers of one enqueued esq_verify_batch call."""
 
@@ -287,17 +322,12 @@ class PendingBatch:
 
     def result(self, check: bool = True) -> list:
         self.event.synchronize()
-        sb = self.summaries.cpu().numpy().tobytes()
-        rb = self.records.cpu().numpy().tobytes()
-        out = []
-        rstride = ESQ_RECORDS_CAP * RECORD_BYTES
-        for i in range(self.count):
-            r = _parse(sb[i * SUMMARY_BYTES:(i + 1) * SUMMARY_BYTES], rb[i * rstride:(i + 1) * rstride])
+        out = _parse_many(self.summaries, self.records, self.count)
+        for i, r in enumerate(out):
             if self.per_n is not None and self.per_n[i] is not None:
                 r["per_n"] = self.per_n[i]
             if check and r["status"]:
                 raise EsqError(-100, "device status 0x%x for interval %d" % (r["status"], i))
-            out.append(r)
         return out
 
 
@@ -335,15 +365,10 @@ class PreparedBatch:
 
     def results(self, check=True):
         torch.cuda.synchronize()
-        sb = self.summaries.cpu().numpy().tobytes()
-        rb = self.records.cpu().numpy().tobytes()
-        rstride = ESQ_RECORDS_CAP * RECORD_BYTES
-        out = []
-        for i in range(self.count):
-            r = _parse(sb[i * SUMMARY_BYTES:(i + 1) * SUMMARY_BYTES], rb[i * rstride:(i + 1) * rstride])
+        out = _parse_many(self.summaries, self.records, self.count)
+        for i, r in enumerate(out):
             if check and r["status"]:
                 raise EsqError(-100, "device status 0x%x for interval %d" % (r["status"], i))
-            out.append(r)
         return out
 
     def close(self):

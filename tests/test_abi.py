@@ -73,3 +73,18 @@ def test_product_path_has_no_cpu_fallback():
     """The binding never imports the oracle."""
     src = open(os.path.join(ROOT, "paper_2411_01964_amd", "esq.py")).read()
     assert "oracle" not in src.replace("no CPU fallback", "")
+
+
+def test_numpy_views_match_header_layout():
+    import numpy as np
+    assert esq.SUMMARY_DTYPE.itemsize == ctypes.sizeof(esq.Summary)
+    assert esq.SUMMARY_DTYPE.fields["ksum"][1] == esq.Summary.ksum.offset
+    assert esq.SUMMARY_DTYPE.fields["status"][1] == esq.Summary.status.offset
+    assert esq.RECORD_DTYPE.fields["k"][1] == esq.Record.k.offset
+    # a summary written through ctypes reads back through the numpy view
+    s = esq.Summary()
+    s.n0, s.n_odd, s.ksum, s.kmax_seen, s.n_records, s.status = 3, 7, 11, 5, 2, 1
+    s.hist[4] = 9
+    v = np.frombuffer(bytes(s), dtype=esq.SUMMARY_DTYPE)[0]
+    assert (v["n0"], v["n_odd"], v["ksum"], v["kmax_seen"], v["n_records"], v["status"]) == (3, 7, 11, 5, 2, 1)
+    assert v["hist"][4] == 9
