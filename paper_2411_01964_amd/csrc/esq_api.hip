@@ -218,9 +218,7 @@ void free_ctx(Ctx* c)
     if (c->d_primes)
         (void)hipFree(c->d_primes);
     if (c->d_wheel)
-        (void)hipFree(c->d_wheel);
-    if (c->d_wheel2)
-        (void)hipFree(c->d_wheel2);
+        (void)hipFree(c->d_wheel);  // d_wheel2 lives in the same allocation
     delete c;
 }
 
@@ -458,23 +456,26 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
 
     // LDS of the segment kernel: bitmap + medium-prime tables (+ tasks if they fit)
     const size_t nmed = med_end - kFirstMedium;
-    const size_t lds_base = (size_t)rw * 8 + nmed * 8 + ((nmed + 1) / 2) * 8;
+    const size_t lds_base = (size_t)(rw + kVerifyCtrlWords) * 8 + nmed * 8 + ((nmed + 1) / 2) * 8;
     if (lds_base > kVerifyLdsMax)
         return fail(ESQ_EINVAL, "segment too large for LDS with these medium primes");
     const uint32_t n_tasks = mt ? mt->n_tasks : 0;
-    const bool tasks_in_lds = lds_base + (size_t)n_tasks * 8 <= kVerifyLdsMax;
-    const size_t lds_bytes = lds_base + (tasks_in_lds ? (size_t)n_tasks * 8 : 0);
-
-    // work items: runs of consecutive segments
-    int occ;
-    {
+    auto occupancy = [&](size_t bytes) {
         std::lock_guard<std::mutex> lk(g_mu);
-        const auto key = std::make_pair((uint32_t)par.block, lds_bytes);
+        const auto key = std::make_pair((uint32_t)par.block, bytes);
         auto it = c->occupancy.find(key);
         if (it == c->occupancy.end())
-            it = c->occupancy.emplace(key, verify_occupancy((uint32_t)par.block, lds_bytes)).first;
-        occ = it->second;
-    }
+            it = c->occupancy.emplace(key, verify_occupancy((uint32_t)par.block, bytes)).first;
+        return it->second;
+    };
+    // the task table goes into LDS when it fits and costs no resident workgroup
+    const size_t lds_with = lds_base + (size_t)n_tasks * 8;
+    const bool tasks_in_lds = n_tasks == 0 || (lds_with <= kVerifyLdsMax &&
+                                               occupancy(lds_with) >= occupancy(lds_base));
+    const size_t lds_bytes = tasks_in_lds ? lds_with : lds_base;
+
+    // work items: runs of consecutive segments
+    const int occ = occupancy(lds_bytes);
     const uint64_t resident = (uint64_t)c->n_cu * (uint64_t)occ;
     std::vector<uint4>& items = P->items;
     items.clear();
@@ -707,9 +708,13 @@ int esq_init(int device, uint64_t max_hi)
             g_ctx = nullptr;
             return hip_fail(e, "hipFuncSetAttribute");
         }
-        e = hipMalloc(&g_ctx->d_wheel, (size_t)(kWheelPeriod + kWheelExtra) * 8);
+        // both tables in one 2 MiB allocation (a single large page for the
+        // translation caches of every CU)
+        static_assert((kWheelPeriod + kWheelExtra + kWheel2Period + kWheelExtra) * 8 <= kWheelAlloc,
+                      "wheel tables exceed their allocation");
+        e = hipMalloc(&g_ctx->d_wheel, kWheelAlloc);
         if (e == hipSuccess)
-            e = hipMalloc(&g_ctx->d_wheel2, (size_t)(kWheel2Period + kWheelExtra) * 8);
+            g_ctx->d_wheel2 = g_ctx->d_wheel + (kWheelPeriod + kWheelExtra);
         if (e != hipSuccess) {
             free_ctx(g_ctx);
             g_ctx = nullptr;

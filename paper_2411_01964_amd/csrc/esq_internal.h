@@ -25,6 +25,7 @@ namespace esq {
 constexpr uint32_t kWheelPeriod = 9u * 25u * 49u;  // 11025 words: the table stays in L2
 constexpr uint32_t kWheelExtra = 16640;   // >= largest region in 64-bit words
 constexpr uint32_t kWheel2Period = 121u * 169u;  // 20449 words: second table (11^2, 13^2)
+constexpr size_t kWheelAlloc = 2u << 20;  // bytes holding both tables
 constexpr uint32_t kFirstMedium = 5;      // primes[0 .. 5) = 3, 5, 7, 11, 13: the two tables
 constexpr int kMaxKh = 13;                // deepest in-LDS level supported
 constexpr int kMaxMedium = 1536;          // medium primes per launch (LDS offsets)
@@ -109,5 +110,6 @@ hipError_t configure_kernels();
 int verify_occupancy(uint32_t block, size_t lds_bytes);
 size_t verify_lds_bytes(const Launch& L);
 constexpr size_t kVerifyLdsMax = 159 * 1024;  // dynamic LDS per workgroup
+constexpr uint32_t kVerifyCtrlWords = 24;       // k_verify's LDS control block, in 8-byte words
 
 }  // namespace esq

@@ -58,6 +58,8 @@ hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, hipStream_t s)
     return hipGetLastError();
 }
 
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
+
 // popcount(x) + acc in one v_bcnt_u32_b32
 __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc)
 {
@@ -290,23 +292,27 @@ __device__ __forceinline__ void store_depths(uint8_t* out, const uint32_t (&D)[1
 
 __device__ __forceinline__ void mark(uint32_t* bm32, uint32_t pos)
 {
-    atomicOr(&bm32[pos >> 5], 1u << (pos & 31));
+    // the word index through an opaque shift, so that the address becomes one
+    // shift-and-add instead of shift, mask and add
+    uint32_t wi;
+    asm("v_lshrrev_b32 %0, 5, %1" : "=v"(wi) : "v"(pos));
+    atomicOr(&bm32[wi], 1u << (pos & 31));
 }
 
-// LDS layout of k_verify: the region bitmap (rw words), then the medium
-// primes' (q, S mod q), their current first-hit offsets, and -- when it fits
-// -- the lane-task table.
+// LDS layout of k_verify: the region bitmap (rw words), a control block of
+// kVerifyCtrlWords words (per-item first-n slots, level counts, the item),
+// then the medium primes' (q, S mod q), their current first-hit offsets, and
+// -- when it fits -- the lane-task table.
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // MODE 0: verify, aggregates only; MODE 1: verify + per-n bytes;
 // MODE 2: Algorithm 1 alone, bitmap to HBM.
 template <int MODE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 4 : 6))) void k_verify(Launch L)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 4 : 8))) void k_verify(Launch L)
 {
+    // No static LDS: the bitmap sits at LDS address 0, so a bit position
+    // turns into a word address without a base offset.
     extern __shared__ uint64_t lds[];
-    __shared__ unsigned long long s_first[kMaxKh + 2];
-    __shared__ uint32_t s_cnt[kMaxKh + 1];
-    __shared__ uint32_t s_item[4];
 
     const uint32_t tid = threadIdx.x, T = blockDim.x, lane = tid & 63u;
     const uint32_t S = 1u << L.log2S, SW = S >> 6;
@@ -317,10 +323,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
     const uint32_t wstep = SW % kWheelPeriod;
     uint64_t* bm = lds;
     uint32_t* bm32 = reinterpret_cast<uint32_t*>(bm);
-    uint2* s_medq = reinterpret_cast<uint2*>(lds + L.rw);
+    constexpr uint32_t kCntAt = kMaxKh + 2, kItemAt = kCntAt + (kMaxKh + 2) / 2;
+    static_assert(kItemAt + 2 <= kVerifyCtrlWords, "k_verify control block");
+    unsigned long long* s_first = reinterpret_cast<unsigned long long*>(lds + L.rw);  // kMaxKh + 2
+    uint32_t* s_cnt = reinterpret_cast<uint32_t*>(lds + L.rw + kCntAt);               // kMaxKh + 1
+    uint32_t* s_item = reinterpret_cast<uint32_t*>(lds + L.rw + kItemAt);             // 4
+    uint2* s_medq = reinterpret_cast<uint2*>(lds + L.rw + kVerifyCtrlWords);
     uint32_t* s_f = reinterpret_cast<uint32_t*>(s_medq + nmed);
-    uint2* s_task = reinterpret_cast<uint2*>(lds + L.rw + nmed + (nmed + 1) / 2);
-    const uint2* tasks = L.tasks_in_lds ? s_task : L.tasks;
+    uint2* s_task = reinterpret_cast<uint2*>(lds + L.rw + kVerifyCtrlWords + nmed + (nmed + 1) / 2);
 
     // per-launch tables into LDS (the bitmap region is rewritten per segment)
     for (uint32_t i = tid; i < nmed; i += T)
@@ -364,7 +374,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
 
         // per-lane counts of levels 1 .. kRegLevels; deeper levels, reached by
         // few words, count straight into s_cnt
-        constexpr int kRegLevels = 4;
+        constexpr int kRegLevels = 5;
         uint32_t cnt[kRegLevels + 1];
 #pragma unroll
         for (int k = 0; k <= kRegLevels; k++)
@@ -375,6 +385,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             const int64_t Bs = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S;
             const int64_t gw0 = Bs / 64;  // exact: Bs is a multiple of 64
             const uint32_t wb = (uint32_t)(((uint64_t)IV.wheel_base0 + (uint64_t)seg * wstep) % kWheelPeriod);
+
+            // 0. the segment's hit-slot count and this lane's first slot, fetched
+            //    now so that their latency overlaps the wheel loads
+            const uint32_t gs = IV.seg_base + seg;
+            uint32_t nb = 0, slot_pos = R;
+            if (L.bucket_cnt) {
+                // read-only here: a scalar (constant address space) load
+                nb = *(const __attribute__((address_space(4))) uint32_t*)(uintptr_t)(L.bucket_cnt + gs);
+                if (nb <= cap && tid < nb)
+                    slot_pos = L.bucket_slot[(uint64_t)gs * cap + tid];
+            }
 
             // 1. the wheel: odd multiples of 9, 25, 49 and of 121, 169 from the
             //    two tables (words below odd index 0 are all marked); each
@@ -387,24 +408,34 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             const char* src2 = reinterpret_cast<const char*>(L.wheel2 + g2);
             char* dst = reinterpret_cast<char*>(bm);
             if (gw0 >= 0) {
-                const uint32_t passes = L.rw / (4 * T);
-                const uint32_t st = 8 * T;
-                uint32_t off = 8 * tid;
-                for (uint32_t ps = 0; ps < passes; ps++, off += 4 * st) {
-                    uint64_t v[4], x[4];
+                // 16-byte loads (two words per lane; the tables need only
+                // 8-byte alignment for global loads), 16-byte LDS stores
+                const uint32_t st = 16 * T;
+                const uint32_t pairs = L.rw / 2;
+                constexpr int kInitPairs = 2;  // pairs per lane in flight (VGPR budget)
+                const uint32_t passes = pairs / (kInitPairs * T);
+                uint32_t off = 16 * tid;
+                for (uint32_t ps = 0; ps < passes; ps++, off += kInitPairs * st) {
+                    u64x2 v[kInitPairs], x[kInitPairs];
 #pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        v[u] = *reinterpret_cast<const uint64_t*>(src + off + u * st);
-                        x[u] = *reinterpret_cast<const uint64_t*>(src2 + off + u * st);
+                    for (int u = 0; u < kInitPairs; u++) {
+                        v[u] = *reinterpret_cast<const u64x2*>(src + off + u * st);
+                        x[u] = *reinterpret_cast<const u64x2*>(src2 + off + u * st);
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; u++)
-                        *reinterpret_cast<uint64_t*>(dst + off + u * st) = v[u] | x[u];
+                    for (int u = 0; u < kInitPairs; u++)
+                        *reinterpret_cast<u64x2*>(dst + off + u * st) = v[u] | x[u];
                 }
-                for (; off < 8 * L.rw; off += st)
-                    *reinterpret_cast<uint64_t*>(dst + off) =
-                        *reinterpret_cast<const uint64_t*>(src + off) |
-                        *reinterpret_cast<const uint64_t*>(src2 + off);
+                for (; off < 16 * pairs; off += st)
+                    *reinterpret_cast<u64x2*>(dst + off) =
+                        *reinterpret_cast<const u64x2*>(src + off) |
+                        *reinterpret_cast<const u64x2*>(src2 + off);
+                if ((L.rw & 1u) && tid == 0) {
+                    const uint32_t o = 8 * (L.rw - 1);
+                    *reinterpret_cast<uint64_t*>(dst + o) =
+                        *reinterpret_cast<const uint64_t*>(src + o) |
+                        *reinterpret_cast<const uint64_t*>(src2 + o);
+                }
             } else {
                 for (uint32_t w = tid; w < L.rw; w += T)
                     bm[w] = (gw0 + (int64_t)w < 0)
@@ -432,23 +463,28 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
 
             // 2. odd multiples of p^2: medium primes by lane-tasks, larger ones
             //    from the segment's hit slots (directly if the slots overflowed)
-            for (uint32_t e = tid; e < L.n_tasks; e += T) {
-                const uint2 tk = tasks[e];
-                const uint32_t idx = tk.x & 0xffffu, v = tk.x >> 16, c = tk.y;
-                const uint32_t q = s_medq[idx].x;
-                const uint64_t p0 = (uint64_t)s_f[idx] + (uint64_t)v * q;
-                if (p0 >= R)
-                    continue;
-                const uint32_t step = c * q;
-                for (uint32_t pos = (uint32_t)p0; pos < R; pos += step)
-                    mark(bm32, pos);
-            }
+            // A prime with h = ceil(R / q) hits per region has c <= h tasks, so
+            // c q <= R + q and f + v q < R + q: 32-bit positions suffice.
+            auto mark_tasks = [&](const uint2* tk_table) {
+                for (uint32_t e = tid; e < L.n_tasks; e += T) {
+                    const uint2 tk = tk_table[e];
+                    const uint32_t idx = tk.x & 0xffffu, v = tk.x >> 16, c = tk.y;
+                    const uint32_t q = s_medq[idx].x;
+                    const uint32_t step = c * q;
+                    for (uint32_t pos = s_f[idx] + v * q; pos < R; pos += step)
+                        mark(bm32, pos);
+                }
+            };
+            if (L.tasks_in_lds)
+                mark_tasks(s_task);
+            else
+                mark_tasks(L.tasks);
             if (L.bucket_cnt) {
-                const uint32_t gs = IV.seg_base + seg;
-                const uint32_t nb = L.bucket_cnt[gs];
                 if (nb <= cap) {
+                    if (slot_pos < R)
+                        mark(bm32, slot_pos);
                     const uint32_t* sl = L.bucket_slot + (uint64_t)gs * cap;
-                    for (uint32_t e = tid; e < nb; e += T) {
+                    for (uint32_t e = tid + T; e < nb; e += T) {
                         const uint32_t pos = sl[e];
                         if (pos < R)
                             mark(bm32, pos);
@@ -588,13 +624,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 const uint64_t U = ((uint64_t)uhi << 32) | ulo;
                 if (alive && U) {
                     // still unresolved after the in-LDS steps: exact tail pass
+                    // one reservation of popcount(U) list entries per word
                     const uint64_t j0 = As + (uint64_t)mw * 64;
-                    uint64_t x = U;
-                    atomicAdd(&IV.acc->tail_count, (unsigned long long)__popcll(U));
-                    while (x) {
+                    const unsigned long long c = (unsigned long long)__popcll(U);
+                    atomicAdd(&IV.acc->tail_count, c);
+                    unsigned long long idx = atomicAdd(L.tail_count, c);
+                    for (uint64_t x = U; x; idx++) {
                         const int bit = __ffsll((unsigned long long)x) - 1;
                         x &= x - 1;
-                        const unsigned long long idx = atomicAdd(L.tail_count, 1ull);
                         if (idx < L.tail_cap) {
                             L.tail_n[idx] = j0 + (uint64_t)bit;
                             L.tail_iv[idx] = ivi;
@@ -650,7 +687,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
 size_t verify_lds_bytes(const Launch& L)
 {
     const size_t nmed = L.med_end - kFirstMedium;
-    return (size_t)L.rw * 8 + nmed * 8 + ((nmed + 1) / 2) * 8 +
+    return (size_t)(L.rw + kVerifyCtrlWords) * 8 + nmed * 8 + ((nmed + 1) / 2) * 8 +
            (L.tasks_in_lds ? (size_t)L.n_tasks * 8 : 0);
 }
 
