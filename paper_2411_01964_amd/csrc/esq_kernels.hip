@@ -545,6 +545,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 constexpr bool FAST = decltype(fast_c)::value;
                 constexpr bool STEADY = decltype(steady_c)::value;
                 const uint32_t mw = tid + itw * T;
+                // the word's first n-index, for the rare paths only (an opaque
+                // copy keeps the 64-bit arithmetic out of the common path)
+                auto j0_of = [&]() {
+                    uint32_t m = mw;
+                    asm volatile("" : "+v"(m));
+                    return As + (uint64_t)m * 64;
+                };
                 const bool act = FAST || mw < SW;
                 const uint32_t w = HW + (act ? mw : 0u);
                 uint64_t V;
@@ -613,7 +620,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                             const uint32_t l = rfl((uint32_t)(__ffsll((unsigned long long)bal) - 1));
                             if (lane == l) {
                                 const uint64_t U = ((uint64_t)uhi << 32) | ulo;
-                                const uint64_t n_first = As + (uint64_t)mw * 64 +
+                                const uint64_t n_first = j0_of() +
                                                          (uint64_t)(__ffsll((unsigned long long)U) - 1);
                                 atomicMin(&s_first[k + 1], (unsigned long long)n_first);
                             }
@@ -621,11 +628,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         }
                     }
                 }
+                // the loop ends early (alive false) for all but the rarest words
                 const uint64_t U = ((uint64_t)uhi << 32) | ulo;
-                if (alive && U) {
+                if (__builtin_expect(alive, 0) && U) {
                     // still unresolved after the in-LDS steps: exact tail pass
                     // one reservation of popcount(U) list entries per word
-                    const uint64_t j0 = As + (uint64_t)mw * 64;
+                    const uint64_t j0 = j0_of();
                     const unsigned long long c = (unsigned long long)__popcll(U);
                     atomicAdd(&IV.acc->tail_count, c);
                     unsigned long long idx = atomicAdd(L.tail_count, c);
@@ -651,13 +659,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 }
             };
             constexpr uint32_t kSteadyBits = 0x3Cu;  // levels 2 .. 5
-            for (uint32_t itw = 0; itw < iters; itw++) {
-                if (!fast)
-                    word_pass(std::false_type{}, std::false_type{}, itw);
-                else if ((rfl(found) & kSteadyBits) == kSteadyBits)
-                    word_pass(std::true_type{}, std::true_type{}, itw);
-                else
+            uint32_t itw = 0;
+            if (fast) {
+                for (; itw < iters && (rfl(found) & kSteadyBits) != kSteadyBits; itw++)
                     word_pass(std::true_type{}, std::false_type{}, itw);
+                for (; itw < iters; itw++)
+                    word_pass(std::true_type{}, std::true_type{}, itw);
+            } else {
+                for (; itw < iters; itw++)
+                    word_pass(std::false_type{}, std::false_type{}, itw);
             }
             __syncthreads();
         }
