@@ -21,7 +21,7 @@ from . import esq
 
 SPACE = {
     "seg_log2": (16, 17, 18, 19),
-    "block": (128, 256, 512),
+    "block": (128, 256, 512, 1024),
     "medium_max": (2047, 4095, 8191),
 }
 BATCH_SPACE = dict(SPACE, items_per_wg=(1, 2, 4, 8))

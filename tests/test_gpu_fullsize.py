@@ -23,23 +23,19 @@ def lib_ready():
 
 
 def table2():
-    rows = read_golden("table2_probabilities.txt")
-    # printed to 5 significant digits: keep the rounding half-unit
-    out = {}
-    for r in rows:
-        mant, ex = r[2].split("e")
-        out[int(r[0])] = (float(r[2]), 0.5 * 10.0 ** (int(ex) - (len(mant.replace(".", "")) - 1)))
-    out[1] = (8.0 / math.pi ** 2, 0.0)  # d_1 = 8 / pi^2 (Section 2)
-    return out
+    """P(least exponent = l), l <= 9, recomputed from Section 2's formulas
+    (oracle/constants.py; its digits are pinned to Table 2 on the CPU)."""
+    from oracle import constants
+    return {l: float(b) for l, _, b in constants.table(m=10**5, lmax=9)}
 
 
 def check_density(hist, N):
     p = table2()
     for k in range(1, 9):
-        pk, rnd = p[k]
+        pk = p[k]
         mean = N * pk
         sigma = math.sqrt(N * pk * (1 - pk))
-        assert abs(hist[k] - mean) <= 6 * sigma + N * rnd + 1, (k, hist[k], mean, sigma)
+        assert abs(hist[k] - mean) <= 6 * sigma + 1, (k, hist[k], mean, sigma)
 
 
 def check_records_with_oracle(res):

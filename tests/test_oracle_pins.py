@@ -219,10 +219,11 @@ def test_crt_construction_forces_depth():
 
 
 def test_density_against_table2():
-    """Least-k frequencies of random odd n near 2^40 against Table 2's
-    c_l - c_(l-1), binomial sigma (a statistical check, never equality)."""
-    rows = read_golden("table2_probabilities.txt")
-    p = {int(r[0]): float(r[2]) for r in rows}
+    """Least-k frequencies of random odd n near 2^40 against c_l - c_(l-1)
+    of Section 2 (recomputed by oracle/constants.py, pinned to Table 2 in
+    test_constants.py), binomial sigma (a statistical check, never equality)."""
+    from oracle import constants
+    p = {l: float(b) for l, _, b in constants.table(m=10**5, lmax=8)}
     ns = workloads.random_odd(seed=21, count=1 << 14, lo=1 << 40, hi=(1 << 40) + (1 << 36))
     got = np.bincount(oracle.mink_many(ns), minlength=21)
     N = len(ns)
