@@ -175,7 +175,10 @@ void esq_batch_destroy(esq_batch *batch);
  *                (11..11000); larger primes go through per-segment hit slots
  *   "bucket_cap" hit slots per segment (0 = sized from the expected count);
  *                a segment whose slots overflow marks those primes directly
- *   "items_per_wg" batched form: work items per resident workgroup
+ *   "items_per_wg" batched form: work items (runs of consecutive segments)
+ *                per resident workgroup
+ *   "runs_per_wg" single interval: runs of consecutive segments per resident
+ *                workgroup (1..64)
  * Applies to calls made after it.  Returns ESQ_EINVAL for an unknown name
  * or a value out of range.
  */

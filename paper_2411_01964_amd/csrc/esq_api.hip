@@ -45,6 +45,7 @@ struct Params {
     int64_t medium_max = 4095;  // largest prime marked per segment (others: hit slots)
     int64_t bucket_cap = 0;     // hit slots per segment; 0 = from the expected count
     int64_t items_per_wg = 4;   // batch: work items per resident workgroup
+    int64_t runs_per_wg = 1;    // one interval: runs per resident workgroup
 };
 
 struct MedTable {
@@ -63,6 +64,7 @@ struct Ctx {
     uint32_t* d_primes = nullptr;
     uint64_t* d_wheel = nullptr;
     uint64_t* d_wheel2 = nullptr;
+    hipMemPool_t pool = nullptr;    // per-call scratch: stream-ordered, kept cached
     std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
     std::map<std::pair<uint32_t, size_t>, int> occupancy;  // (block, LDS bytes) -> workgroups per CU
 };
@@ -219,6 +221,10 @@ void free_ctx(Ctx* c)
         (void)hipFree(c->d_primes);
     if (c->d_wheel)
         (void)hipFree(c->d_wheel);  // d_wheel2 lives in the same allocation
+    if (c->pool) {
+        (void)hipDeviceSynchronize();  // no call may still hold pool memory
+        (void)hipMemPoolDestroy(c->pool);
+    }
     delete c;
 }
 
@@ -481,10 +487,16 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     items.clear();
     uint32_t n_items = 0;
     if (n_iv == 1) {
-        n_items = (uint32_t)std::min<uint64_t>(nseg_total, resident);
+        // runs_per_wg runs per resident workgroup (a device-scope queue
+        // operation costs microseconds, so runs stay few), each at most
+        // kFlushSegs segments
+        n_items = (uint32_t)std::min<uint64_t>(
+            nseg_total, std::max<uint64_t>(resident * (uint64_t)par.runs_per_wg,
+                                           (nseg_total + kFlushSegs - 1) / kFlushSegs));
     } else {
         const uint64_t target = std::max<uint64_t>(1, resident * (uint64_t)par.items_per_wg);
-        const uint64_t run = std::max<uint64_t>(1, (nseg_total + target - 1) / target);
+        const uint64_t run = std::min<uint64_t>(
+            kFlushSegs, std::max<uint64_t>(1, (nseg_total + target - 1) / target));
         for (uint32_t i = 0; i < n_iv; i++)
             for (uint64_t b = 0; b < ivs[i].nseg; b += run) {
                 uint4 x;
@@ -614,9 +626,9 @@ int enqueue(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vecto
     if (rc)
         return rc;
     char* base = nullptr;
-    hipError_t e = hipMallocAsync((void**)&base, P.bytes, s);
+    hipError_t e = hipMallocFromPoolAsync((void**)&base, P.bytes, c->pool, s);
     if (e != hipSuccess || !base)
-        return fail(ESQ_ENOMEM, std::string("hipMallocAsync(scratch): ") + hipGetErrorString(e));
+        return fail(ESQ_ENOMEM, std::string("hipMallocFromPoolAsync(scratch): ") + hipGetErrorString(e));
     bind(&P, base);
     const bool by_value = P.ivs.size() == 1;
     if (!by_value) {
@@ -708,6 +720,22 @@ int esq_init(int device, uint64_t max_hi)
             g_ctx = nullptr;
             return hip_fail(e, "hipFuncSetAttribute");
         }
+        // a private pool for the per-call scratch that keeps freed memory
+        // (the default pool would hand it back to the driver at each
+        // synchronization and map it again on the next call)
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = device;
+        if ((e = hipMemPoolCreate(&g_ctx->pool, &props)) != hipSuccess) {
+            g_ctx->pool = nullptr;
+            free_ctx(g_ctx);
+            g_ctx = nullptr;
+            return hip_fail(e, "hipMemPoolCreate");
+        }
+        uint64_t keep = ~0ull;
+        (void)hipMemPoolSetAttribute(g_ctx->pool, hipMemPoolAttrReleaseThreshold, &keep);
         // both tables in one 2 MiB allocation (a single large page for the
         // translation caches of every CU)
         static_assert((kWheelPeriod + kWheelExtra + kWheel2Period + kWheelExtra) * 8 <= kWheelAlloc,
@@ -993,6 +1021,10 @@ int esq_set_param(const char* name, int64_t value)
         if (value < 1 || value > 1024)
             return fail(ESQ_EINVAL, "items_per_wg out of range");
         g_par.items_per_wg = value;
+    } else if (n == "runs_per_wg") {
+        if (value < 1 || value > 64)
+            return fail(ESQ_EINVAL, "runs_per_wg out of range");
+        g_par.runs_per_wg = value;
     } else {
         return fail(ESQ_EINVAL, "unknown parameter " + n);
     }
@@ -1014,6 +1046,7 @@ int64_t esq_get_param(const char* name)
     if (n == "medium_max") return g_par.medium_max;
     if (n == "bucket_cap") return g_par.bucket_cap;
     if (n == "items_per_wg") return g_par.items_per_wg;
+    if (n == "runs_per_wg") return g_par.runs_per_wg;
     return -1;
 }
 

@@ -31,6 +31,7 @@ constexpr int kMaxKh = 13;                // deepest in-LDS level supported
 constexpr int kMaxMedium = 1536;          // medium primes per launch (LDS offsets)
 constexpr unsigned long long kNone = ~0ull;
 constexpr int kMaxSegLog2 = 20;
+constexpr uint32_t kFlushSegs = 4096;     // segments per run and per flush of partial totals
 constexpr int kMinSegLog2 = 10;
 constexpr uint32_t kFinalizeSortCap = 16384;  // LDS sort capacity of the finalize pass
 constexpr uint64_t kCofactorPrime = 1u << 20; // primes above this come from cofactor enumeration
@@ -71,7 +72,7 @@ struct Launch {
     uint32_t hlo_words, hup_words, rw;  // rw = hlo_words + S/64 + hup_words
     uint32_t n_iv;                // intervals
     uint32_t n_items;             // work items in the queue
-    uint32_t run;                 // single interval: segments per item (0 = use items[])
+    uint32_t pad0;
     uint32_t mode;                // 0 verify, 1 verify + per-n, 2 sieve
     uint32_t med_end;             // medium primes primes[kFirstMedium .. med_end)
     uint32_t n_tasks;

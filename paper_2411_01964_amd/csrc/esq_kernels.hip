@@ -339,19 +339,53 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
         for (uint32_t i = tid; i < L.n_tasks; i += T)
             s_task[i] = L.tasks[i];
 
+    // per-lane counts of levels 1 .. kRegLevels; deeper levels, reached by few
+    // words, count straight into s_cnt
+    constexpr int kRegLevels = 5;
+    uint32_t cnt[kRegLevels + 1];
+    uint32_t found = 0;       // levels whose least n this wave has already offered
+    uint32_t cur_iv = ~0u;    // interval of the partial totals (~0: none)
+    uint32_t acc_segs = 0;    // segments in the partial totals
+    auto flush = [&](uint32_t iv) {
+        if (MODE != 2) {
+            Acc* acc = L.iv[iv].acc;
+#pragma unroll
+            for (int k = 1; k <= kRegLevels; k++) {
+                if (k > (int)klds)
+                    break;
+                uint32_t v = cnt[k];
+                for (int o = 32; o > 0; o >>= 1)
+                    v += __shfl_xor(v, o);
+                if (lane == 0 && v)
+                    atomicAdd(&s_cnt[k], v);
+            }
+            __syncthreads();
+            if (tid >= 1 && tid <= klds && s_cnt[tid])
+                atomicAdd(&acc->cnt[tid], (unsigned long long)s_cnt[tid]);
+            if (tid >= 2 && tid <= klds + 1 && s_first[tid] != kNone)
+                atomicMin(&acc->first[tid], s_first[tid]);
+        }
+        __syncthreads();
+    };
+
     for (;;) {
         if (tid == 0) {
-            const uint32_t it = atomicAdd(L.queue, 1u);
             uint32_t ok = 0, ivi = 0, b = 0, cnt = 0;
-            if (it < L.n_items) {
-                ok = 1;
-                if (L.items) {
+            if (L.items) {
+                const uint32_t it = atomicAdd(L.queue, 1u);
+                if (it < L.n_items) {
                     const uint4 x = L.items[it];
+                    ok = 1;
                     ivi = x.x;
                     b = x.y;
                     cnt = x.z;
-                } else {
+                }
+            } else {
+                // one interval: run `it` of L.n_items equal runs
+                const uint32_t it = atomicAdd(L.queue, 1u);
+                if (it < L.n_items) {
                     const uint64_t ns = L.iv[0].nseg;
+                    ok = 1;
                     b = (uint32_t)((uint64_t)it * ns / L.n_items);
                     cnt = (uint32_t)((uint64_t)(it + 1) * ns / L.n_items) - b;
                 }
@@ -361,27 +395,52 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             s_item[2] = cnt;
             s_item[3] = ok;
         }
-        if (tid < kMaxKh + 2)
-            s_first[tid] = kNone;
-        if (tid <= kMaxKh)
-            s_cnt[tid] = 0;
         __syncthreads();
-        if (!rfl(s_item[3]))
-            break;
+        const uint32_t item_ok = rfl(s_item[3]);
         const uint32_t ivi = rfl(s_item[0]), seg0 = rfl(s_item[1]), nsegs = rfl(s_item[2]);
+        // the partial totals of cur_iv go to its accumulators when the next
+        // run belongs to another interval, when they would exceed kFlushSegs
+        // segments (32-bit counters), and at exit: one round of global
+        // atomics per flush instead of one per run
+        if (cur_iv != ~0u && (!item_ok || ivi != cur_iv || acc_segs + nsegs > kFlushSegs)) {
+            flush(cur_iv);
+            cur_iv = ~0u;
+        }
+        if (!item_ok)
+            break;
+        if (cur_iv == ~0u) {
+            if (tid < kMaxKh + 2)
+                s_first[tid] = kNone;
+            if (tid <= kMaxKh)
+                s_cnt[tid] = 0;
+#pragma unroll
+            for (int k = 0; k <= kRegLevels; k++)
+                cnt[k] = 0;
+            found = 0;
+            acc_segs = 0;
+            cur_iv = ivi;
+            __syncthreads();
+        }
+        acc_segs += nsegs;
         const Interval IV = L.iv[ivi];
         const uint32_t cap = L.bucket_cap;
 
-        // per-lane counts of levels 1 .. kRegLevels; deeper levels, reached by
-        // few words, count straight into s_cnt
-        constexpr int kRegLevels = 5;
-        uint32_t cnt[kRegLevels + 1];
-#pragma unroll
-        for (int k = 0; k <= kRegLevels; k++)
-            cnt[k] = 0;
-        uint32_t found = 0;  // levels whose least n this wave has already offered
-
         for (uint32_t seg = seg0; seg < seg0 + nsegs; seg++) {
+            // The issue arbiter favours older waves, so of the workgroups
+            // sharing a CU the first-launched would finish far ahead of the
+            // last.  Raising the priority of a workgroup with more of its run
+            // left keeps them level, and the CU busy until the end.
+            {
+                const uint32_t q = min(((seg0 + nsegs - seg) * 4u) / nsegs, 3u);
+                if (q == 0)
+                    __builtin_amdgcn_s_setprio(0);
+                else if (q == 1)
+                    __builtin_amdgcn_s_setprio(1);
+                else if (q == 2)
+                    __builtin_amdgcn_s_setprio(2);
+                else
+                    __builtin_amdgcn_s_setprio(3);
+            }
             const int64_t Bs = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S;
             const int64_t gw0 = Bs / 64;  // exact: Bs is a multiple of 64
             const uint32_t wb = (uint32_t)(((uint64_t)IV.wheel_base0 + (uint64_t)seg * wstep) % kWheelPeriod);
@@ -672,24 +731,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             __syncthreads();
         }
 
-        // 4. the item's totals -> the interval's accumulators
-        if (MODE != 2) {
-#pragma unroll
-            for (int k = 1; k <= kRegLevels; k++) {
-                if (k > (int)klds)
-                    break;
-                uint32_t v = cnt[k];
-                for (int o = 32; o > 0; o >>= 1)
-                    v += __shfl_xor(v, o);
-                if (lane == 0 && v)
-                    atomicAdd(&s_cnt[k], v);
-            }
-            __syncthreads();
-            if (tid >= 1 && tid <= klds && s_cnt[tid])
-                atomicAdd(&IV.acc->cnt[tid], (unsigned long long)s_cnt[tid]);
-            if (tid >= 2 && tid <= klds + 1 && s_first[tid] != kNone)
-                atomicMin(&IV.acc->first[tid], s_first[tid]);
-        }
+        // the item's s_item slots are reused by the next fetch
         __syncthreads();
     }
 }
