@@ -72,17 +72,17 @@ def cpu_baseline(lo, hi, seconds, nthreads):
     import oracle
     from paper_2411_01964_amd import workloads
 
-    probe = workloads.random_odd(seed=3, count=max(2 * nthreads, 32), lo=lo, hi=hi)
-    oracle.mink_many(probe[:2], nthreads=1)  # builds the oracle's prime list
-    t0 = time.perf_counter()
-    oracle.mink_many(probe, nthreads=nthreads)
-    rate = len(probe) / max(time.perf_counter() - t0, 1e-9)
-    count = int(min(max(64, rate * seconds), 1 << 22))
-    sample = workloads.random_odd(seed=31, count=count, lo=lo, hi=hi)
-    t0 = time.perf_counter()
-    ks = oracle.mink_many(sample, nthreads=nthreads)
-    dt = time.perf_counter() - t0
-    assert int(np.count_nonzero(ks == 0)) == 0
+    oracle.mink_many(workloads.random_odd(seed=3, count=2, lo=lo, hi=hi), nthreads=1)  # prime list
+    # chunks of a seeded sample until the target time is reached
+    sample = workloads.random_odd(seed=31, count=1 << 22, lo=lo, hi=hi)
+    count, dt, chunk = 0, 0.0, 64 * nthreads
+    while dt < seconds and count < len(sample):
+        part = sample[count:count + chunk]
+        t0 = time.perf_counter()
+        ks = oracle.mink_many(part, nthreads=nthreads)
+        dt += time.perf_counter() - t0
+        assert int(np.count_nonzero(ks == 0)) == 0
+        count += len(part)
     return {
         "value": count / dt,
         "unit": "odd n/s",
