@@ -600,19 +600,23 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             const uint32_t iters = (SW + T - 1) / T;
             // STEADY: the least n of depth 2 .. 5 have been offered already, so
             // steps 1 .. 4 run without any branch.
+            const uint64_t* pbase = bm + HW + tid - 1;  // FAST: word before pass 0's word
             auto word_pass = [&](auto fast_c, auto steady_c, uint32_t itw) {
                 constexpr bool FAST = decltype(fast_c)::value;
                 constexpr bool STEADY = decltype(steady_c)::value;
-                const uint32_t mw = tid + itw * T;
-                // the word's first n-index, for the rare paths only (an opaque
-                // copy keeps the 64-bit arithmetic out of the common path)
+                // the word's first n-index, for the rare paths only (formed from
+                // an opaque copy of tid, so that no index arithmetic is hoisted
+                // into the common path)
                 auto j0_of = [&]() {
-                    uint32_t m = mw;
-                    asm volatile("" : "+v"(m));
-                    return As + (uint64_t)m * 64;
+                    uint32_t t = tid;
+                    asm volatile("" : "+v"(t));
+                    return As + (uint64_t)(t + itw * T) * 64;
                 };
+                const uint32_t mw = tid + itw * T;
                 const bool act = FAST || mw < SW;
-                const uint32_t w = HW + (act ? mw : 0u);
+                // pw points at the word before this lane's word (FAST: from the
+                // loop-invariant base, one add per pass)
+                const uint64_t* pw = FAST ? pbase + itw * T : bm + HW + (act ? mw : 0u) - 1;
                 uint64_t V;
                 if (FAST)
                     V = ~0ull;
@@ -622,7 +626,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     V = ~0ull;
                 else
                     V = valid_mask(As + (uint64_t)mw * 64, IV.I0, IV.I1);
-                const uint64_t cur = bm[w], prv = bm[w - 1];
+                const uint64_t cur = pw[1], prv = pw[0];
                 const uint32_t clo = (uint32_t)cur, chi = (uint32_t)(cur >> 32);
                 const uint32_t plo = (uint32_t)prv, phi = (uint32_t)(prv >> 32);
                 uint32_t ulo = (uint32_t)V, uhi = (uint32_t)(V >> 32);
@@ -650,7 +654,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         wlo = plo;
                         whi = phi;
                     } else {
-                        const uint64_t x = (ulo | uhi) ? bm[w - (1u << (k - 7))] : 0ull;
+                        const uint64_t x = (ulo | uhi) ? pw[1 - (1 << (k - 7))] : 0ull;
                         wlo = (uint32_t)x;
                         whi = (uint32_t)(x >> 32);
                     }
