@@ -15,6 +15,7 @@ tests check this); only latency and throughput depend on the mix.
 from __future__ import annotations
 
 import collections
+import gc
 import threading
 import time
 
@@ -33,6 +34,28 @@ def footprint(lo: int, hi: int, per_n: bool) -> int:
     n0 = max(int(lo), 3) | 1
     n = (int(hi) - n0 + 1) // 2 if int(hi) > n0 else 0
     return int(n * _SCRATCH_PER_N) + _SCRATCH_PER_REQUEST + (n if per_n else 0)
+
+
+_gc_lock = threading.Lock()
+_gc_state = {"servers": 0, "was_enabled": True}
+
+
+def _gc_pause():
+    with _gc_lock:
+        if _gc_state["servers"] == 0:
+            _gc_state["was_enabled"] = gc.isenabled()
+            gc.freeze()
+            gc.disable()
+        _gc_state["servers"] += 1
+
+
+def _gc_resume():
+    with _gc_lock:
+        _gc_state["servers"] -= 1
+        if _gc_state["servers"] == 0:
+            gc.unfreeze()
+            if _gc_state["was_enabled"]:
+                gc.enable()
 
 
 class Request:
@@ -55,7 +78,18 @@ class Server:
     """Continuous-batching server over the batched C-ABI call."""
 
     def __init__(self, n_streams: int = 4, hbm_budget: int = 16 << 30, max_batch: int = 512,
-                 kmax: int = 0, on_done=None):
+                 kmax: int = 0, on_done=None, pause_gc: bool = True):
+        # Python's cyclic garbage collector stops every thread while it scans
+        # the heap: with tens of thousands of requests alive, a full pass takes
+        # 30-150 ms and lands on whichever requests are in flight (it set the
+        # p99 latency).  Requests and results form no reference cycles, so
+        # reference counting frees them; the collector is paused (and the
+        # objects alive at start frozen) while the server runs, and restored
+        # by close().
+        self._gc_paused = False
+        if pause_gc:
+            _gc_pause()
+            self._gc_paused = True
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.busy = [None] * n_streams          # (PendingBatch, [Request]) per stream
         self.budget = int(hbm_budget)
@@ -85,6 +119,9 @@ class Server:
             self.running = False
             self.cv.notify()
         self.thread.join()
+        if self._gc_paused:
+            _gc_resume()
+            self._gc_paused = False
         if self.error is not None:
             raise self.error
 
