@@ -410,7 +410,36 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     uint32_t med_end = std::max<uint32_t>(kFirstMedium, prime_upper(c, std::min<uint64_t>(
                                                   (uint64_t)par.medium_max, pmax_all)));
     med_end = std::min<uint32_t>(med_end, kFirstMedium + (uint32_t)kMaxMedium);
-    const uint32_t direct_end = prime_upper(c, kCofactorPrime);
+    // Bucket primes up to P0 take one first-hit computation (a 64-bit
+    // modulo) each; the primes above P0 are found from their cofactors, one
+    // thread per odd j <= m_hi / P0^2 (two square roots, mostly an empty range
+    // for a short interval).  P0 (a power of 2^(1/2) in [2^10, 2^20]) minimizes
+    // #direct + 0.6 #cofactors for the launch's largest candidate.
+    uint64_t m_hi_max = 0;
+    for (uint32_t i = 0; i < n_iv; i++) {
+        const Interval& v = ivs[i];
+        if (!v.nseg)
+            continue;
+        const int64_t B0 = v.A0 - (int64_t)hlo * 64;
+        const uint64_t E = (uint64_t)(v.nseg - 1) * S + R;
+        m_hi_max = std::max(m_hi_max, 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1);
+    }
+    uint64_t P0 = kCofactorPrime;
+    {
+        double best = 0;
+        for (int h = 20; h <= 40; h++) {
+            const uint64_t cand = (uint64_t)std::ldexp(1.0, h / 2) * (h % 2 ? 1.41421356 : 1.0);
+            const uint32_t de = std::max(med_end, prime_upper(c, cand));
+            const double n_direct = (double)(de - med_end);
+            const double n_cofac = (double)m_hi_max / ((double)cand * (double)cand) / 2;
+            const double cost = n_direct + 0.6 * n_cofac;
+            if (h == 20 || cost < best) {
+                best = cost;
+                P0 = cand;
+            }
+        }
+    }
+    const uint32_t direct_end = prime_upper(c, P0);
     uint32_t max_direct = 0, max_cof = 0;
     bool any_bucket = false;
     uint32_t pmax_end_all = med_end;
@@ -426,7 +455,8 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
             const int64_t B0 = v.A0 - (int64_t)hlo * 64;
             const uint64_t E = (uint64_t)(v.nseg - 1) * S + R;
             const uint64_t m_hi = 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1;
-            const uint64_t jmax = m_hi / (kCofactorPrime * kCofactorPrime);
+            const uint64_t pc = c->primes[v.b_direct_end];  // least cofactor-path prime
+            const uint64_t jmax = m_hi / (pc * pc);
             v.n_cof = (uint32_t)((jmax + 1) / 2);
         }
         if (v.pmax_end > med_end)

@@ -34,7 +34,7 @@ constexpr int kMaxSegLog2 = 20;
 constexpr uint32_t kFlushSegs = 4096;     // segments per run and per flush of partial totals
 constexpr int kMinSegLog2 = 10;
 constexpr uint32_t kFinalizeSortCap = 16384;  // LDS sort capacity of the finalize pass
-constexpr uint64_t kCofactorPrime = 1u << 20; // primes above this come from cofactor enumeration
+constexpr uint64_t kCofactorPrime = 1u << 20; // largest direct/cofactor cut-over considered
 
 // Per-interval accumulators in device scratch.
 struct Acc {
@@ -55,7 +55,7 @@ struct Interval {
     uint32_t wheel_base0;   // floor((A0 - 64 hlo_words) / 64) mod kWheelPeriod
     uint32_t pmax_end;      // primes[0 .. pmax_end) are all the primes this interval needs
     uint32_t b_direct_end;  // bucket primes by first hit: primes[med_end .. b_direct_end)
-    uint32_t n_cof;         // odd cofactors j = 1, 3, ... for primes above kCofactorPrime
+    uint32_t n_cof;         // odd cofactors j = 1, 3, ... for primes from b_direct_end on
     Acc* acc;
     uint8_t* out_mink;      // per-n bytes (n-index - I0), or null
     uint64_t* out_bits;     // sieve output words, or null

@@ -154,13 +154,12 @@ __device__ __forceinline__ void bucket_emit(const Launch& L, const Interval& iv,
     }
 }
 
-// grid.y = interval.  Work units, in order: kHeavyPrimes-wide groups of
-// lanes for each of the first n_heavy bucket primes (many hits: the group
-// strides over them), then one thread per remaining bucket prime up to
-// kCofactorPrime, then kCofactorLanes lanes per odd cofactor j (primes above
-// kCofactorPrime, strided over the group).
+// grid.y = interval.  Work units, in order: kHeavyLanes-wide groups of lanes
+// for each of the first n_heavy bucket primes (many hits: the group strides
+// over them), then one thread per remaining prime of the direct range
+// primes[med_end, b_direct_end), then one thread per odd cofactor j for the
+// primes above it.
 constexpr uint32_t kHeavyLanes = 64;
-constexpr uint32_t kCofactorLanes = 8;
 
 __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint32_t max_direct)
 {
@@ -194,19 +193,27 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
             bucket_emit(L, iv, y);
         return;
     }
+    // odd multiples j p^2 of the primes above the direct range, one thread
+    // per odd cofactor j: the p with j p^2 in [m_lo, m_hi] form one range,
+    // empty for most j when the interval is short
     const uint64_t tc = td - max_direct;
-    const uint64_t c = tc / kCofactorLanes;
-    const uint32_t g = (uint32_t)(tc % kCofactorLanes);
-    if (c >= iv.n_cof || iv.b_direct_end >= iv.pmax_end)
+    if (tc >= iv.n_cof || iv.b_direct_end >= iv.pmax_end)
         return;
-    // odd multiples j p^2 of the primes above kCofactorPrime, for one odd j
-    const uint64_t j = 2 * c + 1;
+    const uint64_t j = 2 * tc + 1;
     const uint64_t m_lo = B0 > 0 ? 2 * (uint64_t)B0 + 1 : 1;
     const uint64_t m_hi = 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1;
-    uint64_t pa = isqrt_floor((m_lo + j - 1) / j);
-    if (pa * pa * j < m_lo)
+    // least pa with j pa^2 >= m_lo and largest pb with j pb^2 <= m_hi: a
+    // double estimate (within one of the answer), then exact corrections
+    uint64_t pa = (uint64_t)sqrt((double)m_lo / (double)j);
+    while (pa > 0 && j * pa * pa >= m_lo)
+        pa--;
+    while (j * pa * pa < m_lo)
         pa++;
-    const uint64_t pb = isqrt_floor(m_hi / j);
+    uint64_t pb = (uint64_t)sqrt((double)m_hi / (double)j) + 1;
+    while (j * pb * pb > m_hi)
+        pb--;
+    if (pa > pb || pb < (uint64_t)L.primes[iv.b_direct_end])
+        return;
     // first prime >= pa among primes[b_direct_end, pmax_end)
     uint32_t lo = iv.b_direct_end, hi = iv.pmax_end;
     while (lo < hi) {
@@ -216,22 +223,18 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
         else
             hi = mid;
     }
-    for (uint32_t i = lo + g; i < iv.pmax_end; i += kCofactorLanes) {
+    for (uint32_t i = lo; i < iv.pmax_end; i++) {
         const uint64_t p = L.primes[i];
         if (p > pb)
             break;
-        const uint64_t m = j * p * p;
-        if (m < m_lo || m > m_hi)
-            continue;
-        bucket_emit(L, iv, (m - 1) / 2 - (uint64_t)B0);
+        bucket_emit(L, iv, (j * p * p - 1) / 2 - (uint64_t)B0);
     }
 }
 
 hipError_t launch_bucket(const Launch& L, uint32_t n_heavy, uint32_t max_direct, uint32_t max_cof,
                          hipStream_t s)
 {
-    const uint64_t threads =
-        (uint64_t)n_heavy * kHeavyLanes + max_direct + (uint64_t)max_cof * kCofactorLanes;
+    const uint64_t threads = (uint64_t)n_heavy * kHeavyLanes + max_direct + (uint64_t)max_cof;
     if (threads == 0 || L.n_iv == 0)
         return hipSuccess;
     const uint32_t bx = (uint32_t)((threads + 255) / 256);
