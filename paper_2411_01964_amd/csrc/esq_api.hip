@@ -61,7 +61,8 @@ struct Ctx {
     uint64_t plimit = 0;            // every odd prime <= plimit is in `primes`
     std::vector<uint32_t> primes;   // odd primes ascending (3, 5, 7, ...)
     std::vector<double> inv_pref;   // inv_pref[i] = sum over t < i of 1 / primes[t]^2
-    uint32_t* d_primes = nullptr;
+    uint32_t* d_primes = nullptr;   // the primes, then their coarse index
+    uint32_t pidx_n = 0;
     uint64_t* d_wheel = nullptr;
     uint64_t* d_wheel2 = nullptr;
     hipMemPool_t pool = nullptr;    // per-call scratch: stream-ordered, kept cached
@@ -413,19 +414,25 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     // Bucket primes up to P0 take one first-hit computation (a 64-bit
     // modulo) each; the primes above P0 are found from their cofactors, one
     // thread per odd j <= m_hi / P0^2 (two square roots, mostly an empty range
-    // for a short interval).  P0 (a power of 2^(1/2) in [2^10, 2^20]) minimizes
-    // #direct + 0.6 #cofactors for the launch's largest candidate.
+    // for a short interval).  When the launch's direct threads at P0 = 2^20
+    // fit in one pass of the device, the pass is latency-bound and 2^20 is
+    // kept; otherwise (many intervals) P0, a power of 2^(1/2) in [2^10, 2^20],
+    // minimizes the work #direct + 0.6 #cofactors for the largest candidate.
     uint64_t m_hi_max = 0;
+    uint32_t n_live = 0;
     for (uint32_t i = 0; i < n_iv; i++) {
         const Interval& v = ivs[i];
         if (!v.nseg)
             continue;
+        n_live++;
         const int64_t B0 = v.A0 - (int64_t)hlo * 64;
         const uint64_t E = (uint64_t)(v.nseg - 1) * S + R;
         m_hi_max = std::max(m_hi_max, 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1);
     }
     uint64_t P0 = kCofactorPrime;
-    {
+    const uint64_t direct_threads_full =
+        (uint64_t)n_live * (uint64_t)(std::max(med_end, prime_upper(c, kCofactorPrime)) - med_end);
+    if (direct_threads_full > (uint64_t)c->n_cu * 2048) {
         double best = 0;
         for (int h = 20; h <= 40; h++) {
             const uint64_t cand = (uint64_t)std::ldexp(1.0, h / 2) * (h % 2 ? 1.41421356 : 1.0);
@@ -458,11 +465,18 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
             const uint64_t pc = c->primes[v.b_direct_end];  // least cofactor-path prime
             const uint64_t jmax = m_hi / (pc * pc);
             v.n_cof = (uint32_t)((jmax + 1) / 2);
+            // cofactor j's range holds about L / (2 sqrt(m j) ln p) primes:
+            // the j with more than 4 share them over 8 lanes
+            const double m_lo = std::max(1.0, 2.0 * (double)B0 + 1);
+            const double span = 2.0 * (double)E;
+            const double per_j = span / (2.0 * std::sqrt(m_lo) * std::log((double)pc));
+            const double j_wide = (per_j / 4.0) * (per_j / 4.0);
+            v.n_cof_wide = (uint32_t)std::min<double>(v.n_cof, std::floor((j_wide + 1) / 2));
         }
         if (v.pmax_end > med_end)
             any_bucket = true;
         max_direct = std::max(max_direct, v.b_direct_end - med_end);
-        max_cof = std::max(max_cof, v.n_cof);
+        max_cof = std::max(max_cof, v.n_cof + 7 * v.n_cof_wide);  // cofactor threads
         E_max = std::max(E_max, (uint64_t)(v.nseg - 1) * S + R);
     }
     // bucket primes with more than 8 hits in the longest interval get a
@@ -579,6 +593,8 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.bucket_cap = cap;
     L.nprimes = (uint32_t)c->primes.size();
     L.primes = c->d_primes;
+    L.pidx = c->d_primes + c->primes.size();
+    L.pidx_n = c->pidx_n;
     L.medq = mt ? mt->medq : nullptr;
     L.tasks = mt ? mt->tasks : nullptr;
     L.wheel = c->d_wheel;
@@ -791,20 +807,31 @@ int esq_init(int device, uint64_t max_hi)
         std::vector<double> pref(pr.size() + 1, 0.0);
         for (size_t i = 0; i < pr.size(); i++)
             pref[i + 1] = pref[i] + 1.0 / ((double)pr[i] * (double)pr[i]);
+        // coarse index for the cofactor pass: idx[v] = first prime >= v * 256
+        const uint32_t pidx_n = (uint32_t)((need >> kPidxShift) + 3);
+        std::vector<uint32_t> idx(pidx_n);
+        for (uint32_t v = 0, i = 0; v < pidx_n; v++) {
+            const uint64_t bound = (uint64_t)v << kPidxShift;
+            while (i < pr.size() && pr[i] < bound)
+                i++;
+            idx[v] = i;
+        }
+        pr.insert(pr.end(), idx.begin(), idx.end());
         uint32_t* d = nullptr;
-        e = hipMalloc(&d, std::max<size_t>(pr.size(), 1) * 4);
+        e = hipMalloc(&d, pr.size() * 4);
         if (e != hipSuccess)
             return fail(ESQ_ENOMEM, "hipMalloc(primes)");
-        if (!pr.empty() &&
-            (e = hipMemcpy(d, pr.data(), pr.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+        if ((e = hipMemcpy(d, pr.data(), pr.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) {
             (void)hipFree(d);
             return hip_fail(e, "hipMemcpy(primes)");
         }
+        pr.resize(pr.size() - pidx_n);
         if (c->d_primes) {
             (void)hipDeviceSynchronize();
             (void)hipFree(c->d_primes);
         }
         c->d_primes = d;
+        c->pidx_n = pidx_n;
         c->primes.swap(pr);
         c->inv_pref.swap(pref);
         c->plimit = need;

@@ -34,6 +34,7 @@ constexpr int kMaxSegLog2 = 20;
 constexpr uint32_t kFlushSegs = 4096;     // segments per run and per flush of partial totals
 constexpr int kMinSegLog2 = 10;
 constexpr uint32_t kFinalizeSortCap = 16384;  // LDS sort capacity of the finalize pass
+constexpr uint32_t kPidxShift = 8;        // coarse prime index: 256 integers per entry
 constexpr uint64_t kCofactorPrime = 1u << 20; // largest direct/cofactor cut-over considered
 
 // Per-interval accumulators in device scratch.
@@ -60,7 +61,7 @@ struct Interval {
     uint8_t* out_mink;      // per-n bytes (n-index - I0), or null
     uint64_t* out_bits;     // sieve output words, or null
     uint32_t out_shift;     // sieve: I0 - A0
-    uint32_t pad;
+    uint32_t n_cof_wide;    // the first n_cof_wide cofactors (widest ranges) take 8 lanes each
 };
 
 // Medium-prime lane-task, packed in a uint2: x = idx | (v << 16), y = c;
@@ -82,6 +83,8 @@ struct Launch {
     const Interval* iv;
     const uint4* items;           // (interval, first segment, segments, 0), or null
     const uint32_t* primes;       // odd primes ascending
+    const uint32_t* pidx;         // pidx[v]: index of the first prime >= v << kPidxShift
+    uint32_t pidx_n;              // entries of pidx
     const uint2* medq;            // per medium prime: (q, S mod q)
     const uint2* tasks;           // medium-prime lane-tasks
     uint32_t tasks_in_lds;        // 1: the task table is copied into LDS

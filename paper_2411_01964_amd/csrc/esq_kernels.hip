@@ -157,9 +157,11 @@ __device__ __forceinline__ void bucket_emit(const Launch& L, const Interval& iv,
 // grid.y = interval.  Work units, in order: kHeavyLanes-wide groups of lanes
 // for each of the first n_heavy bucket primes (many hits: the group strides
 // over them), then one thread per remaining prime of the direct range
-// primes[med_end, b_direct_end), then one thread per odd cofactor j for the
-// primes above it.
+// primes[med_end, b_direct_end), then, for the primes above it, kCofactorLanes
+// lanes for each of the first n_cof_wide odd cofactors j (wide ranges) and one
+// thread for each remaining j.
 constexpr uint32_t kHeavyLanes = 64;
+constexpr uint32_t kCofactorLanes = 8;
 
 __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint32_t max_direct)
 {
@@ -197,9 +199,19 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
     // per odd cofactor j: the p with j p^2 in [m_lo, m_hi] form one range,
     // empty for most j when the interval is short
     const uint64_t tc = td - max_direct;
-    if (tc >= iv.n_cof || iv.b_direct_end >= iv.pmax_end)
+    const uint64_t wide_threads = (uint64_t)iv.n_cof_wide * kCofactorLanes;
+    uint64_t c;
+    uint32_t g = 0, lanes = 1;
+    if (tc < wide_threads) {
+        c = tc / kCofactorLanes;
+        g = (uint32_t)(tc % kCofactorLanes);
+        lanes = kCofactorLanes;
+    } else {
+        c = iv.n_cof_wide + (tc - wide_threads);
+    }
+    if (c >= iv.n_cof || iv.b_direct_end >= iv.pmax_end)
         return;
-    const uint64_t j = 2 * tc + 1;
+    const uint64_t j = 2 * c + 1;
     const uint64_t m_lo = B0 > 0 ? 2 * (uint64_t)B0 + 1 : 1;
     const uint64_t m_hi = 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1;
     // least pa with j pa^2 >= m_lo and largest pb with j pb^2 <= m_hi: a
@@ -214,8 +226,10 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
         pb--;
     if (pa > pb || pb < (uint64_t)L.primes[iv.b_direct_end])
         return;
-    // first prime >= pa among primes[b_direct_end, pmax_end)
-    uint32_t lo = iv.b_direct_end, hi = iv.pmax_end;
+    // first prime >= pa among primes[b_direct_end, pmax_end): the coarse
+    // index narrows the search to one 256-wide stretch of integers
+    const uint64_t v = min(pa >> kPidxShift, (uint64_t)L.pidx_n - 2);
+    uint32_t lo = L.pidx[v], hi = L.pidx[v + 1];
     while (lo < hi) {
         const uint32_t mid = lo + (hi - lo) / 2;
         if ((uint64_t)L.primes[mid] < pa)
@@ -223,7 +237,8 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
         else
             hi = mid;
     }
-    for (uint32_t i = lo; i < iv.pmax_end; i++) {
+    lo = max(lo, iv.b_direct_end);
+    for (uint32_t i = lo + g; i < iv.pmax_end; i += lanes) {
         const uint64_t p = L.primes[i];
         if (p > pb)
             break;
