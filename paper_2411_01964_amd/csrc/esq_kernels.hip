@@ -280,6 +280,15 @@ __device__ __forceinline__ uint64_t valid_mask(uint64_t j0, uint64_t I0, uint64_
 // as aligned 32-bit stores; the rest byte by byte.
 __device__ __forceinline__ void store_depths(uint8_t* out, const uint32_t (&D)[16], uint64_t V)
 {
+    // whole word, 16-byte aligned (every word of an interval whose first
+    // n-index is a multiple of 16): four 16-byte stores
+    if (V == ~0ull && ((uintptr_t)out & 15u) == 0) {
+        uint4* o = reinterpret_cast<uint4*>(out);
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            o[q] = make_uint4(D[4 * q], D[4 * q + 1], D[4 * q + 2], D[4 * q + 3]);
+        return;
+    }
     const uint32_t mis = (uint32_t)((uintptr_t)out & 3u);
     uint8_t* al = out - mis;
 #pragma unroll
