@@ -67,7 +67,7 @@ struct Ctx {
     uint64_t* d_wheel2 = nullptr;
     hipMemPool_t pool = nullptr;    // per-call scratch: stream-ordered, kept cached
     std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
-    std::map<std::pair<uint32_t, size_t>, int> occupancy;  // (block, LDS bytes) -> workgroups per CU
+    std::map<std::tuple<int, uint32_t, size_t>, int> occupancy;  // (mode, block, LDS bytes) -> workgroups per CU
 };
 
 std::mutex g_mu;
@@ -505,21 +505,24 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     }
 
     // LDS of the segment kernel: bitmap + medium-prime tables (+ tasks if they fit)
-    const size_t nmed = med_end - kFirstMedium;
-    const size_t lds_base = (size_t)(rw + kVerifyCtrlWords) * 8 + nmed * 8 + ((nmed + 1) / 2) * 8;
-    if (lds_base > kVerifyLdsMax)
-        return fail(ESQ_EINVAL, "segment too large for LDS with these medium primes");
+    const uint32_t nmed = med_end - kFirstMedium;
     const uint32_t n_tasks = mt ? mt->n_tasks : 0;
+    if (verify_lds_size(rw, nmed, 0, false, (uint32_t)par.block) > kVerifyLdsMax)
+        return fail(ESQ_EINVAL, "segment too large for LDS with these medium primes");
+    // per-n output is staged through LDS (1 KB contiguous per store) when the
+    // staging area fits beside the bitmap
+    const bool stage = mode == 1 && verify_lds_size(rw, nmed, 0, true, (uint32_t)par.block) <= kVerifyLdsMax;
+    const size_t lds_base = verify_lds_size(rw, nmed, 0, stage, (uint32_t)par.block);
     auto occupancy = [&](size_t bytes) {
         std::lock_guard<std::mutex> lk(g_mu);
-        const auto key = std::make_pair((uint32_t)par.block, bytes);
+        const auto key = std::make_tuple(mode, (uint32_t)par.block, bytes);
         auto it = c->occupancy.find(key);
         if (it == c->occupancy.end())
-            it = c->occupancy.emplace(key, verify_occupancy((uint32_t)par.block, bytes)).first;
+            it = c->occupancy.emplace(key, verify_occupancy(mode, (uint32_t)par.block, bytes)).first;
         return it->second;
     };
     // the task table goes into LDS when it fits and costs no resident workgroup
-    const size_t lds_with = lds_base + (size_t)n_tasks * 8;
+    const size_t lds_with = verify_lds_size(rw, nmed, n_tasks, stage, (uint32_t)par.block);
     const bool tasks_in_lds = n_tasks == 0 || (lds_with <= kVerifyLdsMax &&
                                                occupancy(lds_with) >= occupancy(lds_base));
     const size_t lds_bytes = tasks_in_lds ? lds_with : lds_base;
@@ -588,6 +591,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.med_end = med_end;
     L.n_tasks = n_tasks;
     L.tasks_in_lds = tasks_in_lds ? 1u : 0u;
+    L.stage = stage ? 1u : 0u;
     L.k_lds = mode == 2 ? 0 : klds;
     L.kmax_eff = kmax_eff;
     L.bucket_cap = cap;

@@ -73,7 +73,7 @@ struct Launch {
     uint32_t hlo_words, hup_words, rw;  // rw = hlo_words + S/64 + hup_words
     uint32_t n_iv;                // intervals
     uint32_t n_items;             // work items in the queue
-    uint32_t pad0;
+    uint32_t stage;               // per-n mode: depth bytes staged through LDS per wave
     uint32_t mode;                // 0 verify, 1 verify + per-n, 2 sieve
     uint32_t med_end;             // medium primes primes[kFirstMedium .. med_end)
     uint32_t n_tasks;
@@ -111,9 +111,26 @@ hipError_t launch_tail(const Launch& L, hipStream_t s);
 hipError_t launch_finalize(const Launch& L, void* out_summaries, void* out_records,
                            uint64_t* out_exceptions, uint64_t exc_cap, hipStream_t s);
 hipError_t configure_kernels();
-int verify_occupancy(uint32_t block, size_t lds_bytes);
-size_t verify_lds_bytes(const Launch& L);
+int verify_occupancy(int mode, uint32_t block, size_t lds_bytes);
+size_t verify_lds_bytes(const Launch& L, uint32_t block);
 constexpr size_t kVerifyLdsMax = 159 * 1024;  // dynamic LDS per workgroup
 constexpr uint32_t kVerifyCtrlWords = 24;       // k_verify's LDS control block, in 8-byte words
+constexpr uint32_t kStageWordsPerWave = 528;    // per-n mode: one wave's 4096 depth bytes + 2 x 64 B guard
+
+// k_verify's dynamic LDS, in 8-byte words: the region bitmap (rw), the
+// control block, the medium primes' (q, S mod q) and first-hit offsets, the
+// task table when it is held in LDS, and -- when per-n output is staged -- a
+// store-staging area of kStageWordsPerWave words per wave, 16-byte aligned.
+__host__ __device__ inline size_t verify_stage_word(uint32_t rw, uint32_t nmed, uint32_t n_tasks_lds)
+{
+    return ((size_t)rw + kVerifyCtrlWords + nmed + (nmed + 1) / 2 + n_tasks_lds + 1) & ~(size_t)1;
+}
+__host__ __device__ inline size_t verify_lds_size(uint32_t rw, uint32_t nmed, uint32_t n_tasks_lds,
+                                                  bool stage, uint32_t block)
+{
+    if (stage)
+        return (verify_stage_word(rw, nmed, n_tasks_lds) + (size_t)(block / 64) * kStageWordsPerWave) * 8;
+    return ((size_t)rw + kVerifyCtrlWords + nmed + (nmed + 1) / 2 + n_tasks_lds) * 8;
+}
 
 }  // namespace esq

@@ -59,6 +59,7 @@ hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, hipStream_t s)
 }
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // popcount(x) + acc in one v_bcnt_u32_b32
 __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc)
@@ -326,6 +327,84 @@ __device__ __forceinline__ void mark(uint32_t* bm32, uint32_t pos)
     atomicOr(&bm32[wi], 1u << (pos & 31));
 }
 
+// Store bytes [b0, b1) of the 16 bytes v at the 16-byte aligned p (b0, b1
+// wave-uniform): whole dwords as dwords, the rest byte by byte.
+__device__ __forceinline__ void store_part16(uint8_t* p, const u32x4 v, uint32_t b0, uint32_t b1)
+{
+#pragma unroll
+    for (uint32_t t = 0; t < 4; t++) {
+        if (4 * t >= b0 && 4 * t + 4 <= b1) {
+            *reinterpret_cast<uint32_t*>(p + 4 * t) = v[t];
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < 4; j++)
+                if (4 * t + j >= b0 && 4 * t + j < b1)
+                    p[4 * t + j] = (uint8_t)(v[t] >> (8 * j));
+        }
+    }
+}
+
+// Position of 16-byte slot s (-4 <= s < 260) in a staging area: slot s of
+// word s/4 is rotated by s/16, so 16 consecutive lanes writing the 4 slots
+// of their words, or reading 16 consecutive slots, touch 16 distinct groups
+// of LDS banks.
+__device__ __forceinline__ int stage_pos(int s) { return 4 * (s >> 2) + (((s & 3) + (s >> 4)) & 3); }
+
+// The 16 output bytes of aligned chunk c out of the staged slots A = c - 1
+// and B = c, when the run starts delta = 4 KQ - (-delta mod 4) bytes past a
+// 16-byte boundary (KQ = ceil(delta / 4), sh = -delta mod 4): the chunk
+// begins delta bytes before slot c.
+template <int KQ>
+__device__ __forceinline__ u32x4 stage_shift(const u32x4 A, const u32x4 B, uint32_t sh)
+{
+    uint32_t x[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+        x[i] = i < KQ ? A[4 + i - KQ] : B[(i - KQ) & 3];
+    return u32x4{__builtin_amdgcn_alignbyte(x[1], x[0], sh), __builtin_amdgcn_alignbyte(x[2], x[1], sh),
+                 __builtin_amdgcn_alignbyte(x[3], x[2], sh), __builtin_amdgcn_alignbyte(x[4], x[3], sh)};
+}
+
+// Per-n mode: write a wave's 4096 depth bytes (lane l holds bytes 64l ..
+// 64l+63 of the run in D) to out .. out+4095 through the wave's staging area
+// st (slot 0; 4 guard slots on either side), so that each global store
+// writes 1 KB of consecutive bytes.  The run starts delta = out mod 16 bytes
+// past an aligned chunk; the first and last chunks, shared with the
+// neighbouring runs, are written in part.
+template <int KQ>
+__device__ __forceinline__ void stage_store_run(u32x4* st, uint8_t* out, const uint32_t (&D)[16],
+                                                uint32_t lane, uint32_t delta)
+{
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        st[stage_pos(4 * (int)lane + q)] = u32x4{D[4 * q], D[4 * q + 1], D[4 * q + 2], D[4 * q + 3]};
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint8_t* g = out - delta;  // 16-byte aligned
+    u32x4* go = reinterpret_cast<u32x4*>(g);
+    const uint32_t sh = (0u - delta) & 3u;
+    u32x4 last;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int c = 64 * r + (int)lane;
+        const u32x4 B = st[stage_pos(c)];
+        if (KQ == 0) {
+            go[c] = B;
+            continue;
+        }
+        const u32x4 v = stage_shift<KQ>(st[stage_pos(c - 1)], B, sh);
+        if (r == 0 && lane == 0)
+            store_part16(g, v, delta, 16);
+        else
+            go[c] = v;
+        last = B;
+    }
+    if (KQ != 0 && lane == 63)
+        store_part16(g + 4096, stage_shift<KQ>(last, last, sh), 0, delta);
+}
+
 // LDS layout of k_verify: the region bitmap (rw words), a control block of
 // kVerifyCtrlWords words (per-item first-n slots, level counts, the item),
 // then the medium primes' (q, S mod q), their current first-hit offsets, and
@@ -358,6 +437,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
     uint2* s_medq = reinterpret_cast<uint2*>(lds + L.rw + kVerifyCtrlWords);
     uint32_t* s_f = reinterpret_cast<uint32_t*>(s_medq + nmed);
     uint2* s_task = reinterpret_cast<uint2*>(lds + L.rw + kVerifyCtrlWords + nmed + (nmed + 1) / 2);
+    // per-n mode: this wave's 4 KB staging area for the depth bytes
+    u32x4* s_stage = reinterpret_cast<u32x4*>(lds + verify_stage_word(L.rw, nmed, L.tasks_in_lds ? L.n_tasks : 0u)) +
+                     (tid >> 6) * (kStageWordsPerWave / 2) + 4;
 
     // per-launch tables into LDS (the bitmap region is rewritten per segment)
     for (uint32_t i = tid; i < nmed; i += T)
@@ -623,7 +705,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             // evenly over the workgroup, searched to the deepest in-LDS level,
             // takes the fast form: every lane active, every n valid, no
             // per-word index arithmetic, no level bound.
-            const bool fast = MODE == 0 && lo_w == 0 && hi_w == SW && SW % T == 0 && klds == (uint32_t)kMaxKh;
+            const bool fast = lo_w == 0 && hi_w == SW && SW % T == 0 && klds == (uint32_t)kMaxKh;
+            // per-n mode, FAST segments: a wave's 64 words are 4096 consecutive
+            // output bytes, staged through LDS; every run of the segment starts
+            // the same delta bytes past a 16-byte boundary
+            const bool stage_ok = MODE == 1 && L.stage && IV.out_mink;
+            const uint32_t delta = rfl((uint32_t)(((uintptr_t)IV.out_mink + (uintptr_t)(As - IV.I0)) & 15u));
             const uint32_t iters = (SW + T - 1) / T;
             // STEADY: the least n of depth 2 .. 5 have been offered already, so
             // steps 1 .. 4 run without any branch.
@@ -738,14 +825,25 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         }
                     }
                 }
-                if (MODE == 1 && V && IV.out_mink) {
-                    const uint64_t j0 = As + (uint64_t)mw * 64;
+                if (MODE == 1 && IV.out_mink) {
                     if (U) {
 #pragma unroll
                         for (int i = 0; i < 16; i++)
                             D[i] &= ~(spread4((uint32_t)(U >> (4 * i)) & 15u) * 0xffu);
                     }
-                    store_depths(IV.out_mink + ((int64_t)j0 - (int64_t)IV.I0), D, V);
+                    if (FAST && stage_ok) {
+                        uint8_t* o = IV.out_mink + (As - IV.I0) + (uint64_t)(itw * T + (tid & ~63u)) * 64;
+                        switch ((delta + 3) >> 2) {
+                        case 0: stage_store_run<0>(s_stage, o, D, lane, delta); break;
+                        case 1: stage_store_run<1>(s_stage, o, D, lane, delta); break;
+                        case 2: stage_store_run<2>(s_stage, o, D, lane, delta); break;
+                        case 3: stage_store_run<3>(s_stage, o, D, lane, delta); break;
+                        default: stage_store_run<4>(s_stage, o, D, lane, delta); break;
+                        }
+                    } else if (V) {
+                        const uint64_t j0 = As + (uint64_t)mw * 64;
+                        store_depths(IV.out_mink + ((int64_t)j0 - (int64_t)IV.I0), D, V);
+                    }
                 }
             };
             constexpr uint32_t kSteadyBits = 0x3Cu;  // levels 2 .. 5
@@ -767,16 +865,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
     }
 }
 
-size_t verify_lds_bytes(const Launch& L)
+size_t verify_lds_bytes(const Launch& L, uint32_t block)
 {
-    const size_t nmed = L.med_end - kFirstMedium;
-    return (size_t)(L.rw + kVerifyCtrlWords) * 8 + nmed * 8 + ((nmed + 1) / 2) * 8 +
-           (L.tasks_in_lds ? (size_t)L.n_tasks * 8 : 0);
+    return verify_lds_size(L.rw, L.med_end - kFirstMedium, L.tasks_in_lds ? L.n_tasks : 0u, L.stage != 0,
+                           block);
 }
 
 hipError_t launch_verify(const Launch& L, uint32_t grid, uint32_t block, hipStream_t s)
 {
-    const size_t lds = verify_lds_bytes(L);
+    const size_t lds = verify_lds_bytes(L, block);
     if (grid == 0 || L.n_items == 0)
         return hipSuccess;
     switch (L.mode) {
@@ -793,11 +890,15 @@ hipError_t launch_verify(const Launch& L, uint32_t grid, uint32_t block, hipStre
     return hipGetLastError();
 }
 
-int verify_occupancy(uint32_t block, size_t lds_bytes)
+int verify_occupancy(int mode, uint32_t block, size_t lds_bytes)
 {
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_verify<0>, (int)block, lds_bytes) !=
-        hipSuccess)
+    hipError_t e;
+    if (mode == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_verify<1>, (int)block, lds_bytes);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_verify<0>, (int)block, lds_bytes);
+    if (e != hipSuccess)
         return 1;
     return occ > 0 ? occ : 1;
 }

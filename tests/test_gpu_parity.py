@@ -157,6 +157,22 @@ def test_deep_path_crt_construction():
             assert g["per_n"].cpu().numpy()[(c - g["n0"]) // 2] >= 8
 
 
+def test_per_n_every_alignment():
+    """Per-n bytes of one interval against the oracle, then of the same
+    interval started j odd numbers later (every start mod 16 of the output
+    bytes, and a few more), against the first one shifted by j."""
+    knobs()
+    lo, hi = (1 << 40) + 1, (1 << 40) + 1 + (1 << 22)
+    base = esq.verify_range(lo, hi, per_n=True)
+    assert_same(base, oracle.verify_range(lo, hi, per_n=True))
+    ref = base["per_n"]
+    for j in list(range(1, 17)) + [63, 64, 65, 1000, 4097, 262143]:
+        g = esq.verify_range(lo + 2 * j, hi, per_n=True)
+        assert torch.equal(g["per_n"], ref[j:]), j
+        counts = torch.bincount(ref[j:].to(torch.int64), minlength=65).cpu().tolist()
+        assert g["hist"][1:] == counts[1:len(g["hist"])], j
+
+
 def test_split_merge_invariance():
     knobs()
     lo, hi = (1 << 36) + 1, (1 << 36) + (1 << 22)
