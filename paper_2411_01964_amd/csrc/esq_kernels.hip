@@ -744,12 +744,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 const uint32_t clo = (uint32_t)cur, chi = (uint32_t)(cur >> 32);
                 const uint32_t plo = (uint32_t)prv, phi = (uint32_t)(prv >> 32);
                 uint32_t ulo = (uint32_t)V, uhi = (uint32_t)(V >> 32);
-                uint32_t D[16];
-                if (MODE == 1) {
-#pragma unroll
-                    for (int i = 0; i < 16; i++)
-                        D[i] = spread4((uint32_t)(V >> (4 * i)) & 15u);
-                }
+                // per-n depths as bit planes: the step sets U_0 = V, U_1, U_2, ...
+                // are nested, so the least k of an n, the number of sets that
+                // hold it, has bit b equal to the parity of its membership in
+                // the U_j with j = 2^b - 1 (mod 2^b)
+                uint32_t pl[4][2] = {{(uint32_t)V, (uint32_t)(V >> 32)}, {0u, 0u}, {0u, 0u}, {0u, 0u}};
                 found = rfl(found);
                 bool alive = true;  // wave-uniform: some lane still has an n left
 #pragma unroll
@@ -779,10 +778,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     else if (ulo | uhi)
                         atomicAdd(&s_cnt[k], (uint32_t)(__popc(ulo) + __popc(uhi)));
                     if (MODE == 1) {
-                        const uint64_t U = ((uint64_t)uhi << 32) | ulo;
 #pragma unroll
-                        for (int i = 0; i < 16; i++)
-                            D[i] += spread4((uint32_t)(U >> (4 * i)) & 15u);
+                        for (int b = 0; b < 4; b++) {
+                            if ((k & ((1 << b) - 1)) == (1 << b) - 1) {
+                                pl[b][0] ^= ulo;
+                                pl[b][1] ^= uhi;
+                            }
+                        }
                     }
                     // a wave of 4096 n almost never empties before step 4, so
                     // the test for an empty wave starts there
@@ -826,10 +828,27 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     }
                 }
                 if (MODE == 1 && IV.out_mink) {
-                    if (U) {
+                    // n without a representation yet (the tail pass decides
+                    // them) get 0
 #pragma unroll
-                        for (int i = 0; i < 16; i++)
-                            D[i] &= ~(spread4((uint32_t)(U >> (4 * i)) & 15u) * 0xffu);
+                    for (int b = 0; b < 4; b++) {
+                        pl[b][0] &= ~ulo;
+                        pl[b][1] &= ~uhi;
+                    }
+                    // planes -> one byte per n: nibble t of plane b spread to
+                    // bit b of 4 bytes; plane 3 (least k >= 8) is almost never set
+                    uint32_t D[16];
+#pragma unroll
+                    for (int t = 0; t < 16; t++) {
+                        const int h = t >> 3, sh = 4 * (t & 7);
+                        D[t] = (((pl[0][h] >> sh) & 15u) * 0x00204081u & 0x01010101u) |
+                               (((pl[1][h] >> sh) & 15u) * 0x00408102u & 0x02020202u) |
+                               (((pl[2][h] >> sh) & 15u) * 0x00810204u & 0x04040404u);
+                    }
+                    if (__ballot((pl[3][0] | pl[3][1]) != 0)) {
+#pragma unroll
+                        for (int t = 0; t < 16; t++)
+                            D[t] |= spread4((pl[3][t >> 3] >> (4 * (t & 7))) & 15u) << 3;
                     }
                     if (FAST && stage_ok) {
                         uint8_t* o = IV.out_mink + (As - IV.I0) + (uint64_t)(itw * T + (tid & ~63u)) * 64;
