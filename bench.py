@@ -128,6 +128,41 @@ def bench_batched(steps):
             "speedup": t_plain / t_batch, "identical": True}
 
 
+def bench_per_n(lo, hi, n_odd, ref, steps=5):
+    """The same interval in per-n mode: one least-k byte per odd n written to
+    HBM (n_odd bytes per call).  The segment kernel's duration comes from the
+    library's launch events; its bound is the HBM write of the bytes."""
+    import torch
+
+    from paper_2411_01964_amd import esq
+
+    r = esq.verify_range(lo, hi, per_n=True)
+    assert r["hist"] == ref["hist"] and r["records"] == ref["records"]
+    # the first 2^24 bytes sum to the sum of least k over their n
+    head = min(n_odd, 1 << 24)
+    n0 = max(lo, 3) | 1
+    part = esq.verify_range(lo, n0 + 2 * head)
+    assert int(torch.sum(r["per_n"][:head], dtype=torch.int64)) == part["ksum"]
+    del r
+    esq.set_param("profile", 1)
+    esq.profile_take()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = esq.verify_range(lo, hi, per_n=True)
+        del r
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    seg_ms, launches = esq.profile_take()
+    esq.set_param("profile", 0)
+    k_s = seg_ms / max(launches, 1) / 1e3
+    return {"odd_n_per_s": n_odd / wall, "ms_per_call": wall * 1e3, "kernel_ms": k_s * 1e3,
+            "kernel_odd_n_per_s": n_odd / k_s,
+            "roofline": {"bound": "hbm", "achieved": n_odd / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": n_odd / k_s / 8e12, "traffic": None,
+                         "kernel": "k_segment (per-n)"}}
+
+
 def bench_served():
     """Config 5: Poisson arrivals (2000 req/s, seeded), lengths 2^12..2^30
     odd n, starts in [3, 2^50), half asking for per-n least k.  1 s warm-up
@@ -265,6 +300,9 @@ def main():
         log("cpu baseline (oracle, %d threads, ~%.0f s)" % (nthreads, args.cpu_seconds))
         cpu = cpu_baseline(lo, hi, args.cpu_seconds, nthreads)
 
+    log("per-n mode: %d bytes per call" % n_odd)
+    per_n = bench_per_n(lo, hi, n_odd, ref)
+
     extras = {}
     if not args.no_extras:
         log("batched: 4096 intervals")
@@ -300,6 +338,7 @@ def main():
         "cpu_baseline": cpu,
         "latency_p50_ms": extras.get("served", {}).get("p50_ms"),
         "latency_p99_ms": extras.get("served", {}).get("p99_ms"),
+        "per_n": per_n,
         "batched": extras.get("batched"),
         "served": extras.get("served"),
         "result": {"kmax_seen": r0["kmax_seen"], "ksum": r0["ksum"],

@@ -344,11 +344,15 @@ __device__ __forceinline__ void store_part16(uint8_t* p, const u32x4 v, uint32_t
     }
 }
 
-// Position of 16-byte slot s (-4 <= s < 260) in a staging area: slot s of
-// word s/4 is rotated by s/16, so 16 consecutive lanes writing the 4 slots
-// of their words, or reading 16 consecutive slots, touch 16 distinct groups
-// of LDS banks.
-__device__ __forceinline__ int stage_pos(int s) { return 4 * (s >> 2) + (((s & 3) + (s >> 4)) & 3); }
+// Position of 16-byte slot s (-4 <= s < 260) in a staging area: the 4 slots
+// of word w = s/4 are rotated by (w/2 xor w/8) mod 4, so that any 8 (or 16)
+// consecutive lanes writing one slot of their words, or reading consecutive
+// slots, touch distinct groups of LDS banks, with 32 or with 64 banks.
+__device__ __forceinline__ int stage_pos(int s)
+{
+    const int w = s >> 2;
+    return 4 * w + (((s & 3) + ((w >> 1) ^ (w >> 3))) & 3);
+}
 
 // The 16 output bytes of aligned chunk c out of the staged slots A = c - 1
 // and B = c, when the run starts delta = 4 KQ - (-delta mod 4) bytes past a
