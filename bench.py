@@ -44,9 +44,10 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_verify_cfg3.json")
 
 
 def measured_traffic():
-    """HBM bytes per launch of the segment kernel from the rocprofv3 counter
-    runs recorded in profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by the
-    copy-probe factors) -- only while the kernel source is the one measured."""
+    """HBM bytes per launch of the segment kernel (summary and per-n mode)
+    from the rocprofv3 counter runs recorded in profiles/ (FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy-probe factors) -- only while the kernel
+    source is the one measured."""
     import hashlib
     try:
         with open(TRAFFIC) as f:
@@ -57,8 +58,12 @@ def measured_traffic():
         return None
     if t.get("kernel_source_sha256") != sha:
         return None
-    return (t["fetch_kib_per_launch"] * t["fetch_factor"] +
-            t["write_kib_per_launch"] * t["write_factor"]) * 1024.0
+    out = {"summary": (t["fetch_kib_per_launch"] * t["fetch_factor"] +
+                       t["write_kib_per_launch"] * t["write_factor"]) * 1024.0}
+    if t.get("per_n_fetch_kib_per_launch") is not None:
+        out["per_n"] = (t["per_n_fetch_kib_per_launch"] * t["fetch_factor"] +
+                        t["per_n_write_kib_per_launch"] * t["write_factor"]) * 1024.0
+    return out
 
 
 def log(msg):
@@ -290,9 +295,9 @@ def main():
                 "unit": "GB/s", "frac": lds_ach / LDS_PEAK, "traffic": None,
                 "kernel": "k_segment", "kernel_ms": seg_avg_s * 1e3}
     roof, alt = (roof_valu, roof_lds) if roof_valu["frac"] >= roof_lds["frac"] else (roof_lds, roof_valu)
-    traffic = measured_traffic() if args.workload == "cfg3_near_2pow50" else None
-    roof["traffic"] = traffic
-    alt["traffic"] = traffic
+    traffic = (measured_traffic() if args.workload == "cfg3_near_2pow50" else None) or {}
+    roof["traffic"] = traffic.get("summary")
+    alt["traffic"] = traffic.get("summary")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -302,6 +307,7 @@ def main():
 
     log("per-n mode: %d bytes per call" % n_odd)
     per_n = bench_per_n(lo, hi, n_odd, ref)
+    per_n["roofline"]["traffic"] = traffic.get("per_n")
 
     extras = {}
     if not args.no_extras:
