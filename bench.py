@@ -60,6 +60,8 @@ def measured_traffic():
         return None
     out = {"summary": (t["fetch_kib_per_launch"] * t["fetch_factor"] +
                        t["write_kib_per_launch"] * t["write_factor"]) * 1024.0}
+    if t.get("valu_insts_per_launch") is not None:
+        out["valu_lane_ops"] = 64.0 * t["valu_insts_per_launch"]
     if t.get("per_n_fetch_kib_per_launch") is not None:
         out["per_n"] = (t["per_n_fetch_kib_per_launch"] * t["fetch_factor"] +
                         t["per_n_write_kib_per_launch"] * t["write_factor"]) * 1024.0
@@ -298,6 +300,12 @@ def main():
     traffic = (measured_traffic() if args.workload == "cfg3_near_2pow50" else None) or {}
     roof["traffic"] = traffic.get("summary")
     alt["traffic"] = traffic.get("summary")
+    if traffic.get("valu_lane_ops") is not None:
+        # every VALU instruction the kernel issued (SQ_INSTS_VALU x 64 lanes),
+        # not only the search's algorithmic ones
+        issued = traffic["valu_lane_ops"] / seg_avg_s
+        roof_valu["issued"] = {"achieved": issued / 1e12, "frac": issued / VALU_PEAK,
+                               "source": "SQ_INSTS_VALU of the committed counter run"}
 
     cpu = None
     if not args.no_cpu_baseline:
