@@ -160,17 +160,45 @@ def test_deep_path_crt_construction():
 def test_per_n_every_alignment():
     """Per-n bytes of one interval against the oracle, then of the same
     interval started j odd numbers later (every start mod 16 of the output
-    bytes, and a few more), against the first one shifted by j."""
-    knobs()
+    bytes, and a few more), against the first one shifted by j; with one
+    and with eight waves per workgroup."""
     lo, hi = (1 << 40) + 1, (1 << 40) + 1 + (1 << 22)
+    knobs()
     base = esq.verify_range(lo, hi, per_n=True)
     assert_same(base, oracle.verify_range(lo, hi, per_n=True))
     ref = base["per_n"]
-    for j in list(range(1, 17)) + [63, 64, 65, 1000, 4097, 262143]:
-        g = esq.verify_range(lo + 2 * j, hi, per_n=True)
-        assert torch.equal(g["per_n"], ref[j:]), j
-        counts = torch.bincount(ref[j:].to(torch.int64), minlength=65).cpu().tolist()
-        assert g["hist"][1:] == counts[1:len(g["hist"])], j
+    for block in (512, 64):
+        knobs(block=block)
+        for j in list(range(0, 17)) + [63, 64, 65, 1000, 4097, 262143]:
+            g = esq.verify_range(lo + 2 * j, hi, per_n=True)
+            assert torch.equal(g["per_n"], ref[j:]), (block, j)
+            counts = torch.bincount(ref[j:].to(torch.int64), minlength=65).cpu().tolist()
+            assert g["hist"][1:] == counts[1:len(g["hist"])], (block, j)
+    knobs()
+
+
+def test_per_n_unaligned_output_pointer():
+    """The per-n buffer given through the C-ABI at every byte offset mod 16
+    (the output alignment then comes from the pointer, not from lo): same
+    bytes as the aligned call, and nothing written outside the n_odd bytes."""
+    import ctypes
+    knobs()
+    lo, hi = (1 << 44) + 1, (1 << 44) + 1 + (1 << 21)
+    ref = esq.verify_range(lo, hi, per_n=True)["per_n"]
+    n = ref.numel()
+    lib = esq.lib()
+    summary = torch.empty(esq.SUMMARY_BYTES, dtype=torch.uint8, device="cuda")
+    records = torch.empty(esq.ESQ_RECORDS_CAP * esq.RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for off in range(16):
+        buf = torch.full((n + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+        rc = lib.esq_verify_range(lo, hi, 0, ctypes.c_void_p(buf.data_ptr() + 32 + off),
+                                  ctypes.c_void_p(summary.data_ptr()), ctypes.c_void_p(records.data_ptr()),
+                                  None, 0, ctypes.c_void_p(stream.cuda_stream))
+        assert rc == 0, off
+        torch.cuda.synchronize()
+        assert torch.equal(buf[32 + off:32 + off + n], ref), off
+        assert bool((buf[:32 + off] == 0xAB).all()) and bool((buf[32 + off + n:] == 0xAB).all()), off
 
 
 def test_split_merge_invariance():
