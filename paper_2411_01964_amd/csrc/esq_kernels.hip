@@ -589,14 +589,20 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 uint32_t off = 16 * tid;
                 for (uint32_t ps = 0; ps < passes; ps++, off += kInitPairs * st) {
                     u64x2 v[kInitPairs], x[kInitPairs];
+                    uint32_t o[kInitPairs];
 #pragma unroll
                     for (int u = 0; u < kInitPairs; u++) {
-                        v[u] = *reinterpret_cast<const u64x2*>(src + off + u * st);
-                        x[u] = *reinterpret_cast<const u64x2*>(src2 + off + u * st);
+                        // each pair's offset as its own 32-bit value, so that
+                        // its loads keep the scalar-base form
+                        o[u] = off + u * st;
+                        if (u > 0)
+                            asm volatile("" : "+v"(o[u]));
+                        v[u] = *reinterpret_cast<const u64x2*>(src + o[u]);
+                        x[u] = *reinterpret_cast<const u64x2*>(src2 + o[u]);
                     }
 #pragma unroll
                     for (int u = 0; u < kInitPairs; u++)
-                        *reinterpret_cast<u64x2*>(dst + off + u * st) = v[u] | x[u];
+                        *reinterpret_cast<u64x2*>(dst + o[u]) = v[u] | x[u];
                 }
                 for (; off < 16 * pairs; off += st)
                     *reinterpret_cast<u64x2*>(dst + off) =
