@@ -170,6 +170,35 @@ def bench_per_n(lo, hi, n_odd, ref, steps=5):
                          "kernel": "k_segment (per-n)"}}
 
 
+def bench_sieve(lo, hi, steps=5):
+    """Algorithm 1 alone over the same interval of odd m: one bit per odd m
+    written to HBM.  The segment kernel's duration comes from the library's
+    launch events; its bound is the HBM write of the bitmap."""
+    import torch
+
+    from paper_2411_01964_amd import esq
+
+    m0, n, w = esq.sieve_segment(lo, hi)
+    out_bytes = 8 * w.numel()
+    esq.set_param("profile", 1)
+    esq.profile_take()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        esq.sieve_segment(lo, hi, out=w)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    seg_ms, launches = esq.profile_take()
+    esq.set_param("profile", 0)
+    k_s = seg_ms / max(launches, 1) / 1e3
+    del w
+    return {"odd_m_per_s": n / wall, "ms_per_call": wall * 1e3, "kernel_ms": k_s * 1e3,
+            "kernel_odd_m_per_s": n / k_s,
+            "roofline": {"bound": "hbm", "achieved": out_bytes / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": out_bytes / k_s / 8e12, "traffic": None,
+                         "kernel": "k_segment (sieve)"}}
+
+
 def bench_served():
     """Config 5: Poisson arrivals (2000 req/s, seeded), lengths 2^12..2^30
     odd n, starts in [3, 2^50), half asking for per-n least k.  1 s warm-up
@@ -316,6 +345,8 @@ def main():
     log("per-n mode: %d bytes per call" % n_odd)
     per_n = bench_per_n(lo, hi, n_odd, ref)
     per_n["roofline"]["traffic"] = traffic.get("per_n")
+    log("sieve alone: %d bits per call" % n_odd)
+    sieve = bench_sieve(lo, hi)
 
     extras = {}
     if not args.no_extras:
@@ -353,6 +384,7 @@ def main():
         "latency_p50_ms": extras.get("served", {}).get("p50_ms"),
         "latency_p99_ms": extras.get("served", {}).get("p99_ms"),
         "per_n": per_n,
+        "sieve": sieve,
         "batched": extras.get("batched"),
         "served": extras.get("served"),
         "result": {"kmax_seen": r0["kmax_seen"], "ksum": r0["ksum"],

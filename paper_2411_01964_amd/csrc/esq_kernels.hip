@@ -684,17 +684,29 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 // region bits out_shift + 64 lw ... (words lw and lw + 1)
                 const uint32_t sh = IV.out_shift;
                 const uint64_t n_bits = IV.I1 - IV.I0;
-                for (uint32_t lw = tid; lw < SW; lw += T) {
-                    const uint64_t wo = (uint64_t)seg * SW + lw;
-                    if (wo * 64 >= n_bits)
-                        break;
-                    const uint64_t lo = bm[lw], hi = bm[lw + 1];
-                    const uint64_t v = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
-                    uint64_t out = ~v;
-                    const uint64_t rem = n_bits - wo * 64;
-                    if (rem < 64)
-                        out &= (1ull << rem) - 1;
-                    IV.out_bits[wo] = out;
+                const uint64_t wo0 = (uint64_t)seg * SW;
+                if (wo0 * 64 + (uint64_t)SW * 64 <= n_bits && (((uintptr_t)IV.out_bits) & 15u) == 0) {
+                    // a whole segment of output: two words per lane, 16-byte stores
+                    for (uint32_t lw = 2 * tid; lw < SW; lw += 2 * T) {
+                        const uint64_t w0 = bm[lw], w1 = bm[lw + 1], w2 = bm[lw + 2];
+                        u64x2 o;
+                        o.x = ~(sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0);
+                        o.y = ~(sh ? ((w1 >> sh) | (w2 << (64 - sh))) : w1);
+                        *reinterpret_cast<u64x2*>(IV.out_bits + wo0 + lw) = o;
+                    }
+                } else {
+                    for (uint32_t lw = tid; lw < SW; lw += T) {
+                        const uint64_t wo = wo0 + lw;
+                        if (wo * 64 >= n_bits)
+                            break;
+                        const uint64_t lo = bm[lw], hi = bm[lw + 1];
+                        const uint64_t v = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
+                        uint64_t out = ~v;
+                        const uint64_t rem = n_bits - wo * 64;
+                        if (rem < 64)
+                            out &= (1ull << rem) - 1;
+                        IV.out_bits[wo] = out;
+                    }
                 }
                 __syncthreads();
                 continue;

@@ -97,3 +97,59 @@ def test_full_interval_windows_vs_oracle():
             o = oracle.verify_range(a, b, per_n=True)
             assert g["hist"] == o["hist"] and g["records"] == o["records"]
             assert np.array_equal(g["per_n"].cpu().numpy(), o["per_n"])
+
+
+def mobius_np(n):
+    """mu(0..n): -1 for each prime factor, 0 on a square factor (its own sieve)."""
+    mu = np.ones(n + 1, dtype=np.int8)
+    mu[0] = 0
+    is_p = np.ones(n + 1, dtype=bool)
+    is_p[:2] = False
+    for p in range(2, math.isqrt(n) + 1):
+        if is_p[p]:
+            is_p[p * p::p] = False
+    for p in np.nonzero(is_p)[0]:
+        p = int(p)
+        mu[::p] *= -1
+        if p * p <= n:
+            mu[::p * p] = 0
+    return mu
+
+
+def q_odd_np(x, mu):
+    """Odd squarefree m in [1, x]: sum over odd d, d^2 <= x, of
+    mu(d) * #{odd multiples of d^2 up to x}."""
+    if x <= 0:
+        return 0
+    d = np.arange(1, math.isqrt(x) + 1, 2, dtype=np.int64)
+    return int(np.sum(mu[d].astype(np.int64) * ((x // (d * d) + 1) // 2)))
+
+
+def popcount_gpu(words):
+    """Set bits of an int64 CUDA tensor (SWAR on 32-bit lanes, then bytes)."""
+    x = words.view(torch.int32)
+    x = x - ((x >> 1) & 0x55555555)
+    x = (x & 0x33333333) + ((x >> 2) & 0x33333333)
+    x = (x + (x >> 4)) & 0x0F0F0F0F
+    return int(x.view(torch.uint8).sum(dtype=torch.int64))
+
+
+@pytest.mark.parametrize("name", ["cfg2_2pow40", "cfg3_near_2pow50"])
+def test_sieve_full_interval_moebius_count(name):
+    """Algorithm 1 alone over a whole benchmarked interval of odd m: the
+    number of set bits equals the exact Moebius count of odd squarefree m in
+    it, the bits past the end are clear, and sampled bits match the oracle's
+    trial division."""
+    lo, hi = workloads.CONFIGS[name]
+    m0, n, w = esq.sieve_segment(lo, hi)
+    assert m0 == lo | 1 and n == (hi - m0 + 1) // 2
+    mu = mobius_np(math.isqrt(hi) + 1)
+    assert popcount_gpu(w) == q_odd_np(hi - 1, mu) - q_odd_np(lo - 1, mu)
+    if n % 64:
+        assert int(w[-1]) >> (n % 64) == 0
+    i = workloads.random_odd(seed=11, count=512, lo=0, hi=2 * n).astype(np.int64) // 2
+    bits = ((w[torch.from_numpy(i // 64).cuda()] >> torch.from_numpy(i % 64).cuda()) & 1).cpu().numpy()
+    ms = (np.uint64(m0) + 2 * i.astype(np.uint64))
+    assert np.array_equal(bits.astype(np.uint8), oracle.is_squarefree_many(ms))
+    del w
+    torch.cuda.empty_cache()
