@@ -86,9 +86,10 @@ typedef struct esq_summary {
 
 /*
  * Select HIP device `device` and make the library resident on it: the odd
- * primes p <= isqrt(max_hi) (Algorithm 1's prime list, Section 3) and the
- * periodic pattern of odd multiples of 9, 25, 49 and 121.  Idempotent; a
- * larger max_hi extends the table.  max_hi <= ESQ_MAX_HI.  Synchronous.
+ * primes p <= isqrt(max_hi) (Algorithm 1's prime list, Section 3) and two
+ * periodic tables of the odd multiples of 9, 25, 49 and of 121, 169.
+ * Idempotent; a larger max_hi extends the prime table.  max_hi <= ESQ_MAX_HI.
+ * Synchronous.
  */
 int esq_init(int device, uint64_t max_hi);
 
@@ -97,7 +98,9 @@ int esq_init(int device, uint64_t max_hi);
  * d_bits (device, caller-owned) receives ceil(n/64) little-endian uint64
  * words, n = number of odd m in [max(lo,1), hi): bit i (LSB first) of the
  * stream is 1 iff m0 + 2i is squarefree, m0 = first odd >= max(lo, 1).  Bits
- * past the last m are 0.  hi <= the max_hi given to esq_init.
+ * past the last m are 0.  hi <= the max_hi given to esq_init.  d_bits needs
+ * 8-byte alignment; at 16-byte alignment whole segments go out with 16-byte
+ * stores.
  */
 int esq_sieve_segment(uint64_t lo, uint64_t hi, uint64_t *d_bits, void *stream);
 
@@ -108,7 +111,8 @@ int esq_sieve_segment(uint64_t lo, uint64_t hi, uint64_t *d_bits, void *stream);
  *                  (kmax == 0 or k <= kmax).  0 = no limit other than
  *                  positivity.  kmax <= 63.
  *   d_out_mink     device, nullable; n_odd bytes: [i] = least k of n0 + 2i,
- *                  0 where none was found.
+ *                  0 where none was found.  Any alignment; no byte outside
+ *                  the n_odd is written.
  *   out_summary    device, required: one esq_summary.
  *   out_records    device, nullable: ESQ_RECORDS_CAP entries; the first
  *                  n_records are the record-setters in ascending n.
