@@ -354,10 +354,10 @@ __device__ __forceinline__ int stage_pos(int s)
     return 4 * w + (((s & 3) + ((w >> 1) ^ (w >> 3))) & 3);
 }
 
-// The 16 output bytes of aligned chunk c out of the staged slots A = c - 1
-// and B = c, when the run starts delta = 4 KQ - (-delta mod 4) bytes past a
-// 16-byte boundary (KQ = ceil(delta / 4), sh = -delta mod 4): the chunk
-// begins delta bytes before slot c.
+// The 16 output bytes of aligned chunk c, which begins delta bytes before
+// staged slot c, from the slots A = c - 1 and B = c: x holds the five dwords
+// that start KQ = ceil(delta / 4) dwords before slot c, and each output dword
+// is the window of two neighbours that starts sh = (-delta) mod 4 bytes in.
 template <int KQ>
 __device__ __forceinline__ u32x4 stage_shift(const u32x4 A, const u32x4 B, uint32_t sh)
 {

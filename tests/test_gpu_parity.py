@@ -250,3 +250,20 @@ def test_errors_are_reported():
         esq.verify_range(3, 100, exceptions_cap=esq.ESQ_EXCEPTIONS_CAP_MAX + 1)
     L = esq.lib()
     assert L.esq_verify_range(100, 3, 0, None, None, None, None, 0, None) == -1
+
+
+def test_near_the_largest_supported_n():
+    """Windows just below ESQ_MAX_HI = 2^56 (prime table up to 2^28) and at
+    2^53, where doubles no longer hold every odd n: verify and sieve against
+    the oracle."""
+    esq.init(0, esq.ESQ_MAX_HI)
+    knobs()
+    top = esq.ESQ_MAX_HI - 1
+    for lo, hi in ((top - 2 * 700, top), ((1 << 53) + 1, (1 << 53) + 1 + 2 * 600)):
+        g = esq.verify_range(lo, hi, per_n=True, exceptions_cap=16)
+        o = oracle.verify_range(lo, hi, per_n=True)
+        assert_same(g, o)
+        m0, n, w = esq.sieve_segment(lo, hi)
+        om0, on, ow = oracle.sieve_bits(lo, hi)
+        assert (m0, n) == (om0, on)
+        assert np.array_equal(words_np(w), ow)
