@@ -44,7 +44,7 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_verify_cfg3.json")
 
 
 def measured_traffic():
-    """HBM bytes per launch of the segment kernel (summary and per-n mode)
+    """HBM bytes per launch of the segment kernel (summary, per-n and sieve)
     from the rocprofv3 counter runs recorded in profiles/ (FETCH_SIZE and
     WRITE_SIZE, scaled by the copy-probe factors) -- only while the kernel
     source is the one measured."""
@@ -62,6 +62,9 @@ def measured_traffic():
                        t["write_kib_per_launch"] * t["write_factor"]) * 1024.0}
     if t.get("valu_insts_per_launch") is not None:
         out["valu_lane_ops"] = 64.0 * t["valu_insts_per_launch"]
+    if t.get("sieve_fetch_kib_per_launch") is not None:
+        out["sieve"] = (t["sieve_fetch_kib_per_launch"] * t["fetch_factor"] +
+                        t["sieve_write_kib_per_launch"] * t["write_factor"]) * 1024.0
     if t.get("per_n_fetch_kib_per_launch") is not None:
         out["per_n"] = (t["per_n_fetch_kib_per_launch"] * t["fetch_factor"] +
                         t["per_n_write_kib_per_launch"] * t["write_factor"]) * 1024.0
@@ -347,6 +350,7 @@ def main():
     per_n["roofline"]["traffic"] = traffic.get("per_n")
     log("sieve alone: %d bits per call" % n_odd)
     sieve = bench_sieve(lo, hi)
+    sieve["roofline"]["traffic"] = traffic.get("sieve")
 
     extras = {}
     if not args.no_extras:
