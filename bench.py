@@ -22,17 +22,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs at 2.4 GHz; 4 SIMD16 per CU -> 64 int32 lane-ops / clk / CU;
-# LDS 128 bytes / clk / CU.
+# MI355X: 256 CUs at 2.4 GHz.  VALU: the published fp32 vector peak, 157.3
+# TFLOP/s, is 128 lanes x 2 flops per clock per CU, so 128 int32 lane-ops per
+# clock per CU for the full-rate operations (funnel shifts, popcounts and
+# three-operand shift-adds issue at half that rate; esq_measure_ceilings and
+# the benchmark's ceilings block measure both).  LDS: 256 bytes per clock per
+# CU for reads (the measured ds_read_b64 rate exceeds the 128 bytes of CDNA3).
 N_CU, CLK = 256, 2.4e9
-VALU_PEAK = N_CU * 64 * CLK          # 3.93e13 lane-ops/s
-LDS_PEAK = N_CU * 128 * CLK          # 7.86e13 B/s
+VALU_PEAK = N_CU * 128 * CLK         # 7.86e13 lane-ops/s
+LDS_PEAK = N_CU * 256 * CLK          # 1.57e14 B/s
 
 # Work of the bit-sliced method per odd n ("roofline"):
 #  LDS bytes: write the bitmap (1 bit), one 32-bit atomic OR per odd multiple
 #  of p^2 for p >= 13 (density sum_{p>=13} 1/p^2 = 0.02241), read the bitmap
 #  once (1 bit).
 LDS_BYTES_PER_N = 0.125 + 4 * 0.02241 + 0.125
+#  The sieve phase alone (Algorithm 1: bitmap init + marks, p >= 13 and the
+#  large primes' 1.23e-4 hits per n): 0.125 + 4 * (0.02234 + 0.000123) B/n.
+SIEVE_LDS_BYTES_PER_N = 0.125 + 4 * (0.02234 + 0.000123)
 #  VALU lane-ops: 6 per search step per 64-n word (two funnel shifts, two ANDs,
 #  two popcounts) times the expected number of steps per word, 2.928, from the
 #  probabilities of Table 2 (1 + sum_k P(some of 64 n unresolved after k)).
@@ -339,6 +346,37 @@ def main():
         roof_valu["issued"] = {"achieved": issued / 1e12, "frac": issued / VALU_PEAK,
                                "source": "SQ_INSTS_VALU of the committed counter run"}
 
+    # measured ceilings (microbenchmarks) and the kernel's time per phase
+    ceil = esq.measure_ceilings()
+    esq.set_param("phase_clock", 1)
+    esq.phase_take()
+    for _ in range(prof_steps):
+        esq.verify_range_async(lo, hi)
+    torch.cuda.synchronize()
+    ph = esq.phase_take()
+    esq.set_param("phase_clock", 0)
+    tot = max(1, sum(ph.values()))
+    sieve_s = seg_avg_s * (ph["init"] + ph["mark"]) / tot
+    lds_peak = max(ceil["lds_write_b64_Bps"], ceil["lds_read_b64_Bps"])
+    sieve_phase = {
+        "share_init": ph["init"] / tot, "share_mark": ph["mark"] / tot, "share_search": ph["search_or_store"] / tot,
+        "ms": sieve_s * 1e3, "lds_bytes_per_n": SIEVE_LDS_BYTES_PER_N,
+        "achieved_GBps": SIEVE_LDS_BYTES_PER_N * n_odd / sieve_s / 1e9,
+        "peak_measured_GBps": lds_peak / 1e9,
+        "frac_measured": SIEVE_LDS_BYTES_PER_N * n_odd / sieve_s / lds_peak,
+        "frac_nominal": SIEVE_LDS_BYTES_PER_N * n_odd / sieve_s / LDS_PEAK,
+    }
+    ceilings = {"lds_write_b64_GBps": ceil["lds_write_b64_Bps"] / 1e9,
+                "lds_read_b64_GBps": ceil["lds_read_b64_Bps"] / 1e9,
+                "lds_or_b32_GBps": ceil["lds_or_b32_Bps"] / 1e9,
+                "valu_int32_Tops": ceil["valu_int32_ops_per_s"] / 1e12,
+                "nominal_lds_GBps": LDS_PEAK / 1e9, "nominal_valu_Tops": VALU_PEAK / 1e12}
+    roof_valu["peak_measured"] = ceil["valu_int32_ops_per_s"] / 1e12
+    roof_valu["frac_measured"] = valu_ach / ceil["valu_int32_ops_per_s"]
+    roof_lds["peak_measured"] = lds_peak / 1e9
+    roof_lds["frac_measured"] = lds_ach / lds_peak
+    log("ceilings: %s; phases: %s" % (ceilings, sieve_phase))
+
     cpu = None
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)
@@ -387,6 +425,8 @@ def main():
         "cpu_baseline": cpu,
         "latency_p50_ms": extras.get("served", {}).get("p50_ms"),
         "latency_p99_ms": extras.get("served", {}).get("p99_ms"),
+        "ceilings": ceilings,
+        "sieve_phase": sieve_phase,
         "per_n": per_n,
         "sieve": sieve,
         "batched": extras.get("batched"),

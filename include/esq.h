@@ -175,6 +175,8 @@ void esq_batch_destroy(esq_batch *batch);
  *   "entry_hits" target marks per lane-task for medium primes (1..4096)
  *   "tail_cap"   capacity of the per-call list of n unresolved in LDS
  *   "profile"    1 = time each segment-kernel launch (esq_profile_take)
+ *   "phase_clock" 1 = count the segment kernel's time per phase
+ *                (esq_phase_take); costs a few atomics per segment
  *   "medium_max" largest prime whose multiples every segment marks itself
  *                (11..11000); larger primes go through per-segment hit slots
  *   "bucket_cap" hit slots per segment (0 = sized from the expected count);
@@ -198,6 +200,29 @@ int64_t esq_get_param(const char *name); /* -1 for an unknown name */
  * clears the record.  Host pointers.  Returns ESQ_EINVAL for null pointers.
  */
 int esq_profile_take(double *total_ms, uint64_t *launches);
+
+/*
+ * Phase clock for measurement.  While the knob "phase_clock" is 1, the
+ * segment kernel adds, per workgroup and segment, the time from the segment's
+ * start to the end of its wheel init, of its marking (Algorithm 1), and of
+ * its search (Algorithm 2) or bitmap store, in ticks of the device's
+ * constant-rate counter (100 MHz on MI355X).  esq_phase_take waits for the
+ * device, writes the three sums to ticks (host, 3 values) and clears them.
+ * Returns ESQ_EINVAL for a null pointer or before esq_init.
+ */
+int esq_phase_take(uint64_t *ticks);
+
+/*
+ * Measured ceilings of the current device, for the rooflines of the segment
+ * kernel (Section 3's sieve is LDS work, its search VALU work): microbenchmarks
+ * of conflict-free LDS operations and of int32 VALU issue, eight 256-thread
+ * workgroups per CU, best of three timed launches each.  out (host, 4 doubles)
+ * receives: [0] ds_write_b64 bytes/s, [1] ds_read_b64 bytes/s, [2] ds_or_b32
+ * bytes/s, [3] int32 VALU lane-operations/s.  Synchronous; allocates and frees
+ * a small device buffer.  Returns ESQ_EINVAL for a null pointer, ESQ_ENOMEM or
+ * ESQ_EHIP on a HIP failure.
+ */
+int esq_measure_ceilings(double *out);
 
 /* Message for the last non-zero return on the calling thread ("" if none). */
 const char *esq_last_error(void);

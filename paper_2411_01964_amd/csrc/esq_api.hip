@@ -42,6 +42,7 @@ struct Params {
     int entry_hits = 16;
     int64_t tail_cap = 1 << 20;
     int profile = 0;
+    int phase_clock = 0;
     int64_t medium_max = 4095;  // largest prime marked per segment (others: hit slots)
     int64_t bucket_cap = 0;     // hit slots per segment; 0 = from the expected count
     int64_t items_per_wg = 4;   // batch: work items per resident workgroup
@@ -64,6 +65,7 @@ struct Ctx {
     uint32_t* d_primes = nullptr;   // the primes, then their coarse index
     uint32_t pidx_n = 0;
     uint64_t* d_wheel = nullptr;
+    unsigned long long* d_phase = nullptr;  // phase-clock counters, at the end of the d_wheel allocation
     uint64_t* d_wheel2 = nullptr;
     hipMemPool_t pool = nullptr;    // per-call scratch: stream-ordered, kept cached
     std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
@@ -591,6 +593,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.med_end = med_end;
     L.n_tasks = n_tasks;
     L.tasks_in_lds = tasks_in_lds ? 1u : 0u;
+    L.phase = par.phase_clock ? c->d_phase : nullptr;
     L.stage = stage ? 1u : 0u;
     L.k_lds = mode == 2 ? 0 : klds;
     L.kmax_eff = kmax_eff;
@@ -790,9 +793,15 @@ int esq_init(int device, uint64_t max_hi)
         // translation caches of every CU)
         static_assert((kWheelPeriod + kWheelExtra + kWheel2Period + kWheelExtra) * 8 <= kWheelAlloc,
                       "wheel tables exceed their allocation");
+        static_assert((kWheelPeriod + kWheelExtra + kWheel2Period + kWheelExtra) * 8 + kPhaseSlots * 8 <=
+                          kWheelAlloc,
+                      "phase counters exceed the wheel allocation");
         e = hipMalloc(&g_ctx->d_wheel, kWheelAlloc);
-        if (e == hipSuccess)
+        if (e == hipSuccess) {
             g_ctx->d_wheel2 = g_ctx->d_wheel + (kWheelPeriod + kWheelExtra);
+            g_ctx->d_phase = reinterpret_cast<unsigned long long*>(g_ctx->d_wheel) + (kWheelAlloc / 8 - kPhaseSlots);
+            e = hipMemset(g_ctx->d_phase, 0, kPhaseSlots * 8);
+        }
         if (e != hipSuccess) {
             free_ctx(g_ctx);
             g_ctx = nullptr;
@@ -1066,6 +1075,10 @@ int esq_set_param(const char* name, int64_t value)
         if (value < 1 || value > (int64_t)1 << 30)
             return fail(ESQ_EINVAL, "tail_cap out of range");
         g_par.tail_cap = value;
+    } else if (n == "phase_clock") {
+        if (value < 0 || value > 1)
+            return fail(ESQ_EINVAL, "phase_clock must be 0 or 1");
+        g_par.phase_clock = (int)value;
     } else if (n == "profile") {
         if (value < 0 || value > 1)
             return fail(ESQ_EINVAL, "profile must be 0 or 1");
@@ -1104,11 +1117,28 @@ int64_t esq_get_param(const char* name)
     if (n == "entry_hits") return g_par.entry_hits;
     if (n == "tail_cap") return g_par.tail_cap;
     if (n == "profile") return g_par.profile;
+    if (n == "phase_clock") return g_par.phase_clock;
     if (n == "medium_max") return g_par.medium_max;
     if (n == "bucket_cap") return g_par.bucket_cap;
     if (n == "items_per_wg") return g_par.items_per_wg;
     if (n == "runs_per_wg") return g_par.runs_per_wg;
     return -1;
+}
+
+int esq_phase_take(uint64_t* ticks)
+{
+    t_err.clear();
+    if (!ticks)
+        return fail(ESQ_EINVAL, "null pointer");
+    Ctx* c = g_ctx;
+    if (!c)
+        return fail(ESQ_EINVAL, "esq_init has not been called");
+    hipError_t e;
+    if ((e = hipSetDevice(c->device)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess ||
+        (e = hipMemcpy(ticks, c->d_phase, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemset(c->d_phase, 0, kPhaseSlots * 8)) != hipSuccess)
+        return hip_fail(e, "phase counters");
+    return ESQ_OK;
 }
 
 int esq_profile_take(double* total_ms, uint64_t* launches)

@@ -88,6 +88,7 @@ struct Launch {
     const uint2* medq;            // per medium prime: (q, S mod q)
     const uint2* tasks;           // medium-prime lane-tasks
     uint32_t tasks_in_lds;        // 1: the task table is copied into LDS
+    unsigned long long* phase;    // non-null: per-phase clock ticks of the segment loop (init, marking, search or store, segments)
     const uint64_t* wheel;        // kWheelPeriod + kWheelExtra words (9, 25, 49)
     const uint64_t* wheel2;       // kWheel2Period + kWheelExtra words (121, 169)
     uint32_t* bucket_cnt;         // per global segment
@@ -115,6 +116,7 @@ int verify_occupancy(int mode, uint32_t block, size_t lds_bytes);
 size_t verify_lds_bytes(const Launch& L, uint32_t block);
 constexpr size_t kVerifyLdsMax = 159 * 1024;  // dynamic LDS per workgroup
 constexpr uint32_t kVerifyCtrlWords = 24;       // k_verify's LDS control block, in 8-byte words
+constexpr uint32_t kPhaseSlots = 8;             // phase-clock counters (3 used)
 constexpr uint32_t kStageWordsPerWave = 528;    // per-n mode: one wave's 4096 depth bytes + 2 x 64 B guard
 
 // k_verify's dynamic LDS, in 8-byte words: the region bitmap (rw), the

@@ -481,6 +481,20 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
         __syncthreads();
     };
 
+    // phase clock (measurement only): workgroup time per phase of the segment
+    // loop, from the constant-rate counter, summed over workgroups
+    // (every wave reads the counter, so that the previous reading stays in
+    // scalar registers)
+    uint64_t t_ph = 0;
+    auto phase_tick = [&](int ph) {
+        if (L.phase) {
+            const uint64_t t = __builtin_amdgcn_s_memrealtime();
+            if (ph >= 0 && tid == 0)
+                atomicAdd(&L.phase[ph], (unsigned long long)(t - t_ph));
+            t_ph = t;
+        }
+    };
+
     for (;;) {
         if (tid == 0) {
             uint32_t ok = 0, ivi = 0, b = 0, cnt = 0;
@@ -539,6 +553,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
         const uint32_t cap = L.bucket_cap;
 
         for (uint32_t seg = seg0; seg < seg0 + nsegs; seg++) {
+            phase_tick(-1);
             // The issue arbiter favours older waves, so of the workgroups
             // sharing a CU the first-launched would finish far ahead of the
             // last.  Raising the priority of a workgroup with more of its run
@@ -638,6 +653,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 }
             }
             __syncthreads();
+            phase_tick(0);
 
             // 2. odd multiples of p^2: medium primes by lane-tasks, larger ones
             //    from the segment's hit slots (directly if the slots overflowed)
@@ -678,6 +694,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 }
             }
             __syncthreads();
+            phase_tick(1);
 
             if (MODE == 2) {
                 // output word wo = seg * SW + lw covers odd indices I0 + 64 wo ...:
@@ -709,6 +726,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     }
                 }
                 __syncthreads();
+                phase_tick(2);
                 continue;
             }
 
@@ -899,6 +917,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     word_pass(std::false_type{}, std::false_type{}, itw);
             }
             __syncthreads();
+            phase_tick(2);
         }
 
         // the item's s_item slots are reused by the next fetch

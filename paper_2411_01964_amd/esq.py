@@ -25,8 +25,9 @@ STATUS_BUCKET_OVERFLOW = 2
 # every function declared in include/esq.h
 EXPORTS = ("esq_init", "esq_sieve_segment", "esq_verify_range", "esq_verify_batch",
            "esq_batch_create", "esq_batch_launch", "esq_batch_destroy",
-           "esq_set_param", "esq_get_param", "esq_profile_take", "esq_last_error",
-           "esq_shutdown")
+           "esq_set_param", "esq_get_param", "esq_profile_take", "esq_phase_take",
+           "esq_measure_ceilings",
+           "esq_last_error", "esq_shutdown")
 
 
 class Summary(ctypes.Structure):
@@ -105,6 +106,10 @@ def lib():
         L.esq_profile_take.argtypes = [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_uint64)]
         L.esq_profile_take.restype = ctypes.c_int
+        L.esq_phase_take.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+        L.esq_phase_take.restype = ctypes.c_int
+        L.esq_measure_ceilings.argtypes = [ctypes.POINTER(ctypes.c_double)]
+        L.esq_measure_ceilings.restype = ctypes.c_int
         L.esq_last_error.restype = ctypes.c_char_p
         L.esq_shutdown.restype = None
         _lib = L
@@ -152,6 +157,25 @@ def profile_take():
     n = ctypes.c_uint64(0)
     _check(lib().esq_profile_take(ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), int(n.value)
+
+
+def phase_take() -> dict:
+    """Segment-kernel time per phase, summed over workgroups, in ticks of the
+    device's constant-rate counter, while "phase_clock" was 1, since the
+    previous take."""
+    out = (ctypes.c_uint64 * 3)()
+    _check(lib().esq_phase_take(out))
+    return {"init": int(out[0]), "mark": int(out[1]), "search_or_store": int(out[2])}
+
+
+def measure_ceilings() -> dict:
+    """Measured LDS and VALU ceilings of the current device (microbenchmarks):
+    bytes/s of conflict-free ds_write_b64, ds_read_b64, ds_or_b32 and int32
+    VALU lane-operations/s."""
+    out = (ctypes.c_double * 4)()
+    _check(lib().esq_measure_ceilings(out))
+    return {"lds_write_b64_Bps": out[0], "lds_read_b64_Bps": out[1], "lds_or_b32_Bps": out[2],
+            "valu_int32_ops_per_s": out[3]}
 
 
 def sieve_segment(lo: int, hi: int, out=None, stream=None):

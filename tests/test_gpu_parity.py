@@ -252,6 +252,31 @@ def test_errors_are_reported():
     assert L.esq_verify_range(100, 3, 0, None, None, None, None, 0, None) == -1
 
 
+def test_phase_clock_and_ceilings():
+    """The measurement hooks change no result: the phase clock counts every
+    phase of the segment loop, and the ceiling microbenchmarks return
+    plausible rates."""
+    knobs()
+    lo, hi = (1 << 40) + 1, (1 << 40) + 1 + (1 << 24)
+    ref = esq.verify_range(lo, hi, per_n=True)
+    esq.set_param("phase_clock", 1)
+    try:
+        esq.phase_take()
+        g = esq.verify_range(lo, hi, per_n=True)
+        ph = esq.phase_take()
+        esq.sieve_segment(lo, hi)
+        ph2 = esq.phase_take()
+    finally:
+        esq.set_param("phase_clock", 0)
+    assert g["hist"] == ref["hist"] and torch.equal(g["per_n"], ref["per_n"])
+    assert all(v > 0 for v in ph.values()) and all(v > 0 for v in ph2.values())
+    assert esq.phase_take() == {"init": 0, "mark": 0, "search_or_store": 0}
+    c = esq.measure_ceilings()
+    for k in ("lds_write_b64_Bps", "lds_read_b64_Bps", "lds_or_b32_Bps"):
+        assert 1e12 < c[k] < 1e15, (k, c[k])
+    assert 1e12 < c["valu_int32_ops_per_s"] < 1e15
+
+
 def test_near_the_largest_supported_n():
     """Windows just below ESQ_MAX_HI = 2^56 (prime table up to 2^28) and at
     2^53, where doubles no longer hold every odd n: verify and sieve against
