@@ -370,6 +370,8 @@ def main():
                 "lds_read_b64_GBps": ceil["lds_read_b64_Bps"] / 1e9,
                 "lds_or_b32_GBps": ceil["lds_or_b32_Bps"] / 1e9,
                 "valu_int32_Tops": ceil["valu_int32_ops_per_s"] / 1e12,
+                "valu_alignbit_Tops": ceil["valu_alignbit_ops_per_s"] / 1e12,
+                "valu_bcnt_Tops": ceil["valu_bcnt_ops_per_s"] / 1e12,
                 "nominal_lds_GBps": LDS_PEAK / 1e9, "nominal_valu_Tops": VALU_PEAK / 1e12}
     roof_valu["peak_measured"] = ceil["valu_int32_ops_per_s"] / 1e12
     roof_valu["frac_measured"] = valu_ach / ceil["valu_int32_ops_per_s"]

@@ -216,9 +216,10 @@ int esq_phase_take(uint64_t *ticks);
  * Measured ceilings of the current device, for the rooflines of the segment
  * kernel (Section 3's sieve is LDS work, its search VALU work): microbenchmarks
  * of conflict-free LDS operations and of int32 VALU issue, eight 256-thread
- * workgroups per CU, best of three timed launches each.  out (host, 4 doubles)
+ * workgroups per CU, best of three timed launches each.  out (host, 6 doubles)
  * receives: [0] ds_write_b64 bytes/s, [1] ds_read_b64 bytes/s, [2] ds_or_b32
- * bytes/s, [3] int32 VALU lane-operations/s.  Synchronous; allocates and frees
+ * bytes/s, and int32 VALU lane-operations/s of [3] v_add_u32/v_xor_b32,
+ * [4] v_alignbit_b32, [5] v_bcnt_u32_b32.  Synchronous; allocates and frees
  * a small device buffer.  Returns ESQ_EINVAL for a null pointer, ESQ_ENOMEM or
  * ESQ_EHIP on a HIP failure.
  */

@@ -1,6 +1,7 @@
 // Measured ceilings of the device for the rooflines of the segment kernel:
 // LDS bandwidth of conflict-free ds_write_b64, ds_read_b64 and ds_or_b32, and
-// the int32 VALU issue rate.  Each microbenchmark runs eight 256-thread
+// the int32 VALU issue rate of full-rate operations and of the search's
+// funnel shift and popcount.  Each microbenchmark runs eight 256-thread
 // workgroups per CU (8 waves per SIMD) with the operations in inline assembly,
 // so that none is removed or merged by the compiler.
 #include <hip/hip_runtime.h>
@@ -12,10 +13,11 @@
 #include "esq_internal.h"
 
 namespace esq {
-namespace {
+namespace ceil {
 
 constexpr uint32_t kCeilBlock = 256;
 constexpr uint32_t kCeilLdsBytes = 16384;  // 8 operations x 256 lanes x 8 bytes
+constexpr int kCeilings = 6;
 
 // OP 0: ds_write_b64, 1: ds_read_b64, 2: ds_or_b32.  Lane l touches bytes
 // 8l .. 8l+7 (4l .. 4l+3 for ds_or_b32) of each 2 KB (1 KB) block, so every
@@ -85,7 +87,10 @@ __global__ __launch_bounds__(kCeilBlock) void k_ceil_lds(uint64_t* sink, uint32_
     sink[(size_t)blockIdx.x * kCeilBlock + tid] = acc;
 }
 
-// 64 independent int32 VALU operations per iteration (eight chains).
+// 64 independent int32 VALU operations per iteration (eight chains).  OP 0:
+// v_add_u32 / v_xor_b32 (full rate); 1: v_alignbit_b32 and 2: v_bcnt_u32_b32,
+// the search's funnel shift and popcount.
+template <int OP>
 __global__ __launch_bounds__(kCeilBlock) void k_ceil_valu(uint64_t* sink, uint32_t iters)
 {
     const uint32_t tid = threadIdx.x;
@@ -94,7 +99,51 @@ __global__ __launch_bounds__(kCeilBlock) void k_ceil_valu(uint64_t* sink, uint32
     const uint32_t c = 0x9e3779b9u;
     for (uint32_t i = 0; i < iters; i++) {
 #pragma unroll
-        for (int r = 0; r < 4; r++)
+        for (int r = 0; r < 4; r++) {
+            if (OP == 1) {
+                asm volatile(
+                    "v_alignbit_b32 %0, %0, %8, 7\n"
+                    "v_alignbit_b32 %1, %1, %8, 7\n"
+                    "v_alignbit_b32 %2, %2, %8, 7\n"
+                    "v_alignbit_b32 %3, %3, %8, 7\n"
+                    "v_alignbit_b32 %4, %4, %8, 7\n"
+                    "v_alignbit_b32 %5, %5, %8, 7\n"
+                    "v_alignbit_b32 %6, %6, %8, 7\n"
+                    "v_alignbit_b32 %7, %7, %8, 7\n"
+                    "v_alignbit_b32 %0, %0, %8, 9\n"
+                    "v_alignbit_b32 %1, %1, %8, 9\n"
+                    "v_alignbit_b32 %2, %2, %8, 9\n"
+                    "v_alignbit_b32 %3, %3, %8, 9\n"
+                    "v_alignbit_b32 %4, %4, %8, 9\n"
+                    "v_alignbit_b32 %5, %5, %8, 9\n"
+                    "v_alignbit_b32 %6, %6, %8, 9\n"
+                    "v_alignbit_b32 %7, %7, %8, 9\n"
+                    : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3), "+v"(x4), "+v"(x5), "+v"(x6), "+v"(x7)
+                    : "v"(c));
+                continue;
+            }
+            if (OP == 2) {
+                asm volatile(
+                    "v_bcnt_u32_b32 %0, %0, %8\n"
+                    "v_bcnt_u32_b32 %1, %1, %8\n"
+                    "v_bcnt_u32_b32 %2, %2, %8\n"
+                    "v_bcnt_u32_b32 %3, %3, %8\n"
+                    "v_bcnt_u32_b32 %4, %4, %8\n"
+                    "v_bcnt_u32_b32 %5, %5, %8\n"
+                    "v_bcnt_u32_b32 %6, %6, %8\n"
+                    "v_bcnt_u32_b32 %7, %7, %8\n"
+                    "v_bcnt_u32_b32 %0, %0, %8\n"
+                    "v_bcnt_u32_b32 %1, %1, %8\n"
+                    "v_bcnt_u32_b32 %2, %2, %8\n"
+                    "v_bcnt_u32_b32 %3, %3, %8\n"
+                    "v_bcnt_u32_b32 %4, %4, %8\n"
+                    "v_bcnt_u32_b32 %5, %5, %8\n"
+                    "v_bcnt_u32_b32 %6, %6, %8\n"
+                    "v_bcnt_u32_b32 %7, %7, %8\n"
+                    : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3), "+v"(x4), "+v"(x5), "+v"(x6), "+v"(x7)
+                    : "v"(c));
+                continue;
+            }
             asm volatile(
                 "v_add_u32 %0, %0, %8\n"
                 "v_xor_b32 %1, %1, %8\n"
@@ -114,14 +163,16 @@ __global__ __launch_bounds__(kCeilBlock) void k_ceil_valu(uint64_t* sink, uint32
                 "v_add_u32 %7, %7, %8\n"
                 : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3), "+v"(x4), "+v"(x5), "+v"(x6), "+v"(x7)
                 : "v"(c));
+        }
     }
     sink[(size_t)blockIdx.x * kCeilBlock + tid] = (uint64_t)(x0 ^ x1 ^ x2 ^ x3 ^ x4 ^ x5 ^ x6 ^ x7);
 }
 
-}  // namespace
+}  // namespace ceil
 }  // namespace esq
 
 using namespace esq;
+using namespace esq::ceil;
 
 extern "C" int esq_measure_ceilings(double* out)
 {
@@ -142,9 +193,9 @@ extern "C" int esq_measure_ceilings(double* out)
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rc = ESQ_EHIP;
     // bytes (or lane-operations) per thread per iteration
-    const double per_iter[4] = {64.0, 64.0, 32.0, 64.0};
-    const uint32_t iters[4] = {1024, 1024, 1024, 512};
-    for (int t = 0; t < 4 && rc == ESQ_OK; t++) {
+    const double per_iter[kCeilings] = {64.0, 64.0, 32.0, 64.0, 64.0, 64.0};
+    const uint32_t iters[kCeilings] = {1024, 1024, 1024, 512, 256, 256};
+    for (int t = 0; t < kCeilings && rc == ESQ_OK; t++) {
         float best = 0.f;
         for (int rep = 0; rep < 4 && rc == ESQ_OK; rep++) {
             if (hipEventRecord(e0, s) != hipSuccess) {
@@ -157,8 +208,12 @@ extern "C" int esq_measure_ceilings(double* out)
                 hipLaunchKernelGGL(k_ceil_lds<1>, dim3(grid), dim3(kCeilBlock), kCeilLdsBytes, s, sink, iters[t]);
             else if (t == 2)
                 hipLaunchKernelGGL(k_ceil_lds<2>, dim3(grid), dim3(kCeilBlock), kCeilLdsBytes, s, sink, iters[t]);
+            else if (t == 3)
+                hipLaunchKernelGGL(k_ceil_valu<0>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
+            else if (t == 4)
+                hipLaunchKernelGGL(k_ceil_valu<1>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
             else
-                hipLaunchKernelGGL(k_ceil_valu, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
+                hipLaunchKernelGGL(k_ceil_valu<2>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
             float ms = 0.f;
             if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {

@@ -115,7 +115,7 @@ hipError_t configure_kernels();
 int verify_occupancy(int mode, uint32_t block, size_t lds_bytes);
 size_t verify_lds_bytes(const Launch& L, uint32_t block);
 constexpr size_t kVerifyLdsMax = 159 * 1024;  // dynamic LDS per workgroup
-constexpr uint32_t kVerifyCtrlWords = 24;       // k_verify's LDS control block, in 8-byte words
+constexpr uint32_t kVerifyCtrlWords = 28;       // k_verify's LDS control block, in 8-byte words
 constexpr uint32_t kPhaseSlots = 8;             // phase-clock counters (3 used)
 constexpr uint32_t kStageWordsPerWave = 528;    // per-n mode: one wave's 4096 depth bytes + 2 x 64 B guard
 

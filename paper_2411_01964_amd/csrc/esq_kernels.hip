@@ -410,14 +410,15 @@ __device__ __forceinline__ void stage_store_run(u32x4* st, uint8_t* out, const u
 }
 
 // LDS layout of k_verify: the region bitmap (rw words), a control block of
-// kVerifyCtrlWords words (per-item first-n slots, level counts, the item),
+// kVerifyCtrlWords words (per-item first-n slots, level counts, the item,
+// phase-clock sums),
 // then the medium primes' (q, S mod q), their current first-hit offsets, and
 // -- when it fits -- the lane-task table.
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // MODE 0: verify, aggregates only; MODE 1: verify + per-n bytes;
 // MODE 2: Algorithm 1 alone, bitmap to HBM.
-template <int MODE>
+template <int MODE, bool PH = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 4 : 8))) void k_verify(Launch L)
 {
     // No static LDS: the bitmap sits at LDS address 0, so a bit position
@@ -433,11 +434,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
     const uint32_t wstep = SW % kWheelPeriod;
     uint64_t* bm = lds;
     uint32_t* bm32 = reinterpret_cast<uint32_t*>(bm);
-    constexpr uint32_t kCntAt = kMaxKh + 2, kItemAt = kCntAt + (kMaxKh + 2) / 2;
-    static_assert(kItemAt + 2 <= kVerifyCtrlWords, "k_verify control block");
+    constexpr uint32_t kCntAt = kMaxKh + 2, kItemAt = kCntAt + (kMaxKh + 2) / 2, kPhAt = kItemAt + 2;
+    static_assert(kPhAt + 3 <= kVerifyCtrlWords, "k_verify control block");
     unsigned long long* s_first = reinterpret_cast<unsigned long long*>(lds + L.rw);  // kMaxKh + 2
     uint32_t* s_cnt = reinterpret_cast<uint32_t*>(lds + L.rw + kCntAt);               // kMaxKh + 1
     uint32_t* s_item = reinterpret_cast<uint32_t*>(lds + L.rw + kItemAt);             // 4
+    unsigned long long* s_ph = reinterpret_cast<unsigned long long*>(lds + L.rw + kPhAt);  // 3 (phase clock)
     uint2* s_medq = reinterpret_cast<uint2*>(lds + L.rw + kVerifyCtrlWords);
     uint32_t* s_f = reinterpret_cast<uint32_t*>(s_medq + nmed);
     uint2* s_task = reinterpret_cast<uint2*>(lds + L.rw + kVerifyCtrlWords + nmed + (nmed + 1) / 2);
@@ -481,16 +483,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
         __syncthreads();
     };
 
-    // phase clock (measurement only): workgroup time per phase of the segment
-    // loop, from the constant-rate counter, summed over workgroups
-    // (every wave reads the counter, so that the previous reading stays in
-    // scalar registers)
+    // phase clock (the PH instance only, for measurement): workgroup time per
+    // phase of the segment loop from the constant-rate counter, summed in LDS
+    // and added to L.phase once per workgroup at exit
     uint64_t t_ph = 0;
+    if (PH && tid < 3)
+        s_ph[tid] = 0;
     auto phase_tick = [&](int ph) {
-        if (L.phase) {
+        if (PH) {
             const uint64_t t = __builtin_amdgcn_s_memrealtime();
             if (ph >= 0 && tid == 0)
-                atomicAdd(&L.phase[ph], (unsigned long long)(t - t_ph));
+                atomicAdd(&s_ph[ph], (unsigned long long)(t - t_ph));
             t_ph = t;
         }
     };
@@ -533,8 +536,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             flush(cur_iv);
             cur_iv = ~0u;
         }
-        if (!item_ok)
+        if (!item_ok) {
+            if (PH && tid < 3)
+                atomicAdd(&L.phase[tid], s_ph[tid]);
             break;
+        }
         if (cur_iv == ~0u) {
             if (tid < kMaxKh + 2)
                 s_first[tid] = kNone;
@@ -936,15 +942,25 @@ hipError_t launch_verify(const Launch& L, uint32_t grid, uint32_t block, hipStre
     const size_t lds = verify_lds_bytes(L, block);
     if (grid == 0 || L.n_items == 0)
         return hipSuccess;
-    switch (L.mode) {
+    // the phase-clock instances only when the clock is on
+    switch (L.mode * 2 + (L.phase ? 1 : 0)) {
     case 0:
-        hipLaunchKernelGGL(k_verify<0>, dim3(grid), dim3(block), lds, s, L);
+        hipLaunchKernelGGL((k_verify<0, false>), dim3(grid), dim3(block), lds, s, L);
         break;
     case 1:
-        hipLaunchKernelGGL(k_verify<1>, dim3(grid), dim3(block), lds, s, L);
+        hipLaunchKernelGGL((k_verify<0, true>), dim3(grid), dim3(block), lds, s, L);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_verify<1, false>), dim3(grid), dim3(block), lds, s, L);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_verify<1, true>), dim3(grid), dim3(block), lds, s, L);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_verify<2, false>), dim3(grid), dim3(block), lds, s, L);
         break;
     default:
-        hipLaunchKernelGGL(k_verify<2>, dim3(grid), dim3(block), lds, s, L);
+        hipLaunchKernelGGL((k_verify<2, true>), dim3(grid), dim3(block), lds, s, L);
         break;
     }
     return hipGetLastError();
@@ -1191,12 +1207,13 @@ hipError_t configure_kernels()
 {
     hipError_t e;
     const int lds_max = (int)kVerifyLdsMax;
-    e = hipFuncSetAttribute((const void*)k_verify<0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_verify<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_verify<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (e != hipSuccess) return e;
+    const void* fns[6] = {(const void*)k_verify<0, false>, (const void*)k_verify<0, true>,
+                          (const void*)k_verify<1, false>, (const void*)k_verify<1, true>,
+                          (const void*)k_verify<2, false>, (const void*)k_verify<2, true>};
+    for (const void* f : fns) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        if (e != hipSuccess) return e;
+    }
     e = hipFuncSetAttribute((const void*)k_finalize, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(kFinalizeSortCap * 8));
     return e;

@@ -170,12 +170,14 @@ def phase_take() -> dict:
 
 def measure_ceilings() -> dict:
     """Measured LDS and VALU ceilings of the current device (microbenchmarks):
-    bytes/s of conflict-free ds_write_b64, ds_read_b64, ds_or_b32 and int32
-    VALU lane-operations/s."""
-    out = (ctypes.c_double * 4)()
+    bytes/s of conflict-free ds_write_b64, ds_read_b64, ds_or_b32, and int32
+    VALU lane-operations/s of full-rate adds/xors, funnel shifts and
+    popcounts."""
+    out = (ctypes.c_double * 6)()
     _check(lib().esq_measure_ceilings(out))
     return {"lds_write_b64_Bps": out[0], "lds_read_b64_Bps": out[1], "lds_or_b32_Bps": out[2],
-            "valu_int32_ops_per_s": out[3]}
+            "valu_int32_ops_per_s": out[3], "valu_alignbit_ops_per_s": out[4],
+            "valu_bcnt_ops_per_s": out[5]}
 
 
 def sieve_segment(lo: int, hi: int, out=None, stream=None):

@@ -274,7 +274,8 @@ def test_phase_clock_and_ceilings():
     c = esq.measure_ceilings()
     for k in ("lds_write_b64_Bps", "lds_read_b64_Bps", "lds_or_b32_Bps"):
         assert 1e12 < c[k] < 1e15, (k, c[k])
-    assert 1e12 < c["valu_int32_ops_per_s"] < 1e15
+    for k in ("valu_int32_ops_per_s", "valu_alignbit_ops_per_s", "valu_bcnt_ops_per_s"):
+        assert 1e12 < c[k] < 1e15, (k, c[k])
 
 
 def test_near_the_largest_supported_n():
