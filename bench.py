@@ -32,7 +32,7 @@ N_CU, CLK = 256, 2.4e9
 VALU_PEAK = N_CU * 128 * CLK         # 7.86e13 lane-ops/s
 LDS_PEAK = N_CU * 256 * CLK          # 1.57e14 B/s
 
-# Work of the bit-sliced method per odd n ("roofline"):
+# Work of the bit-sliced method per odd n:
 #  LDS bytes: write the bitmap (1 bit), one 32-bit atomic OR per odd multiple
 #  of p^2 for p >= 13 (density sum_{p>=13} 1/p^2 = 0.02241), read the bitmap
 #  once (1 bit).
@@ -47,7 +47,7 @@ VALU_OPS_PER_N = 6 * 2.928 / 64
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_01964_amd", "csrc", "esq_kernels.hip")
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_verify_cfg3.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_verify_odd_2pow33_below_2pow50.json")
 
 
 def measured_traffic():
@@ -111,7 +111,7 @@ def cpu_baseline(lo, hi, seconds, nthreads):
 
 
 def bench_batched(steps):
-    """Config 4: 4096 seeded intervals (lengths 2^16..2^28 odd n, starts in
+    """Batched intervals: 4096 seeded intervals (lengths 2^16..2^28 odd n, starts in
     [2^30, 2^50)) in one prepared batch replayed as a hipGraph, against the
     plain path (one esq_verify_range per interval, back to back on one
     stream).  Results must agree exactly."""
@@ -210,7 +210,7 @@ def bench_sieve(lo, hi, steps=5):
 
 
 def bench_served():
-    """Config 5: Poisson arrivals (2000 req/s, seeded), lengths 2^12..2^30
+    """Served stream: Poisson arrivals (2000 req/s, seeded), lengths 2^12..2^30
     odd n, starts in [3, 2^50), half asking for per-n least k.  1 s warm-up
     plus 10 s measured; p50/p99 latency from arrival to completion.  Then the
     same requests all at once through the server (its capacity) and through
@@ -244,7 +244,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg3_near_2pow50")
+    ap.add_argument("--workload", default="odd_2pow33_below_2pow50")
     ap.add_argument("--streams", type=int, default=3,
                     help="steps alternate over this many HIP streams, so that one step's "
                          "setup kernels overlap another step's segment kernel")
@@ -336,7 +336,7 @@ def main():
                 "unit": "GB/s", "frac": lds_ach / LDS_PEAK, "traffic": None,
                 "kernel": "k_segment", "kernel_ms": seg_avg_s * 1e3}
     roof, alt = (roof_valu, roof_lds) if roof_valu["frac"] >= roof_lds["frac"] else (roof_lds, roof_valu)
-    traffic = (measured_traffic() if args.workload == "cfg3_near_2pow50" else None) or {}
+    traffic = (measured_traffic() if args.workload == "odd_2pow33_below_2pow50" else None) or {}
     roof["traffic"] = traffic.get("summary")
     alt["traffic"] = traffic.get("summary")
     if traffic.get("valu_lane_ops") is not None:

@@ -16,11 +16,11 @@ import numpy as np
 # name -> (lo, hi); every odd n in [lo, hi) with n >= 3 is examined
 CONFIGS = {
     # all odd n in (1, 2^22]: 2,097,151 odd integers
-    "cfg1_small": (3, (1 << 22) + 1),
+    "odd_below_2pow22": (3, (1 << 22) + 1),
     # one contiguous interval of 2^31 odd integers at 2^40
-    "cfg2_2pow40": ((1 << 40) + 1, (1 << 40) + (1 << 32)),
-    # 2^34 odd integers just below the paper's bound 2^50
-    "cfg3_near_2pow50": ((1 << 50) - (1 << 34) + 1, 1 << 50),
+    "odd_2pow31_at_2pow40": ((1 << 40) + 1, (1 << 40) + (1 << 32)),
+    # the last 2^34 integers below the paper's bound 2^50: 2^33 odd integers
+    "odd_2pow33_below_2pow50": ((1 << 50) - (1 << 34) + 1, 1 << 50),
 }
 
 

@@ -58,8 +58,8 @@ def test_table4_and_table3_below_2pow30_on_gpu():
     assert g["kmax_seen"] == 9 and g["n_exceptions"] == 0
 
 
-@pytest.mark.parametrize("name,sample,seed", [("cfg2_2pow40", 4096, 22),
-                                              ("cfg3_near_2pow50", 1024, 33)])
+@pytest.mark.parametrize("name,sample,seed", [("odd_2pow31_at_2pow40", 4096, 22),
+                                              ("odd_2pow33_below_2pow50", 1024, 33)])
 def test_full_interval(name, sample, seed):
     lo, hi = workloads.CONFIGS[name]
     g = esq.verify_range(lo, hi)                       # the benchmarked call
@@ -90,7 +90,7 @@ def test_full_interval(name, sample, seed):
 
 def test_full_interval_windows_vs_oracle():
     """Seeded windows inside the benchmarked intervals, element by element."""
-    for name, width, seed in (("cfg2_2pow40", 1 << 13, 2), ("cfg3_near_2pow50", 1 << 10, 3)):
+    for name, width, seed in (("odd_2pow31_at_2pow40", 1 << 13, 2), ("odd_2pow33_below_2pow50", 1 << 10, 3)):
         lo, hi = workloads.CONFIGS[name]
         for a, b in workloads.random_windows(seed, 2, width, lo, hi):
             g = esq.verify_range(a, b, per_n=True)
@@ -134,7 +134,7 @@ def popcount_gpu(words):
     return int(x.view(torch.uint8).sum(dtype=torch.int64))
 
 
-@pytest.mark.parametrize("name", ["cfg2_2pow40", "cfg3_near_2pow50"])
+@pytest.mark.parametrize("name", ["odd_2pow31_at_2pow40", "odd_2pow33_below_2pow50"])
 def test_sieve_full_interval_moebius_count(name):
     """Algorithm 1 alone over a whole benchmarked interval of odd m: the
     number of set bits equals the exact Moebius count of odd squarefree m in

@@ -79,7 +79,7 @@ def test_sieve_at_2pow40_exact_and_moebius():
 # ------------------------------------------------------ Algorithm 2
 
 def test_config1_full_exact():
-    lo, hi = workloads.CONFIGS["cfg1_small"]
+    lo, hi = workloads.CONFIGS["odd_below_2pow22"]
     g = esq.verify_range(lo, hi, per_n=True, exceptions_cap=64)
     o = oracle.verify_range(lo, hi, per_n=True)
     assert_same(g, o)
