@@ -169,6 +169,8 @@ void esq_batch_destroy(esq_batch *batch);
 /*
  * Tuning knobs (results never depend on them; only speed does).  Names:
  *   "seg_log2"   log2 of the segment length in odd numbers held in LDS (10..20)
+ *   "sieve_seg_log2" the same for esq_sieve_segment (default one larger: its
+ *                bitmap stores do not overlap the next segment's sieving)
  *   "kh"         deepest k resolved from the LDS bitmap (1..13); deeper k go
  *                to the exact tail pass
  *   "block"      threads per workgroup of the segment kernel (64..1024, x64)

@@ -37,6 +37,7 @@ int hip_fail(hipError_t e, const char* what)
 
 struct Params {
     int seg_log2 = 18;
+    int sieve_seg_log2 = 19;  // Algorithm 1 alone: fewer, longer segments (its stores do not overlap)
     int kh = 13;
     int block = 512;
     int entry_hits = 16;
@@ -357,7 +358,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
          Planned* P)
 {
     const uint32_t n_iv = (uint32_t)reqs.size();
-    const uint32_t log2S = (uint32_t)par.seg_log2;
+    const uint32_t log2S = (uint32_t)(mode == 2 ? par.sieve_seg_log2 : par.seg_log2);
     const uint64_t S = 1ull << log2S;
     const uint32_t SW = (uint32_t)(S / 64);
     const uint32_t kmax_eff = kmax ? kmax : 63;
@@ -1059,6 +1060,10 @@ int esq_set_param(const char* name, int64_t value)
         if (value < kMinSegLog2 || value > kMaxSegLog2)
             return fail(ESQ_EINVAL, "seg_log2 out of range");
         g_par.seg_log2 = (int)value;
+    } else if (n == "sieve_seg_log2") {
+        if (value < kMinSegLog2 || value > kMaxSegLog2)
+            return fail(ESQ_EINVAL, "sieve_seg_log2 out of range");
+        g_par.sieve_seg_log2 = (int)value;
     } else if (n == "kh") {
         if (value < 1 || value > kMaxKh)
             return fail(ESQ_EINVAL, "kh out of range");
@@ -1112,6 +1117,7 @@ int64_t esq_get_param(const char* name)
     std::lock_guard<std::mutex> lk(g_mu);
     const std::string n(name);
     if (n == "seg_log2") return g_par.seg_log2;
+    if (n == "sieve_seg_log2") return g_par.sieve_seg_log2;
     if (n == "kh") return g_par.kh;
     if (n == "block") return g_par.block;
     if (n == "entry_hits") return g_par.entry_hits;

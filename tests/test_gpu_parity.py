@@ -13,7 +13,7 @@ from tests.conftest import read_golden
 pytestmark = pytest.mark.gpu
 
 MAX_HI = (1 << 50) + (1 << 33)
-DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
+DEFAULTS = dict(seg_log2=18, sieve_seg_log2=19, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
                 medium_max=4095, bucket_cap=0, items_per_wg=4)
 
 
@@ -57,9 +57,9 @@ def assert_same(g, o, per_n=True):
     (1, 1 << 16), (7, (1 << 16) + 3), (12345, 12345 + 100003),
     ((1 << 30) + 1, (1 << 30) + 200001),
 ])
-@pytest.mark.parametrize("seg_log2", [10, 18])
+@pytest.mark.parametrize("seg_log2", [10, 18, 20])
 def test_sieve_bits_exact(lo, hi, seg_log2):
-    knobs(seg_log2=seg_log2)
+    knobs(sieve_seg_log2=seg_log2)
     m0, n, w = esq.sieve_segment(lo, hi)
     om0, on, ow = oracle.sieve_bits(lo, hi)
     assert (m0 if n else om0, n) == (om0, on)
@@ -69,7 +69,7 @@ def test_sieve_bits_exact(lo, hi, seg_log2):
 
 def test_sieve_at_2pow40_exact_and_moebius():
     lo, hi = (1 << 40) + 3, (1 << 40) + 3 + (1 << 22)
-    knobs(seg_log2=16)
+    knobs(sieve_seg_log2=16)
     m0, n, w = esq.sieve_segment(lo, hi)
     om0, on, ow = oracle.sieve_bits(lo, hi)
     assert (m0, n) == (om0, on)
