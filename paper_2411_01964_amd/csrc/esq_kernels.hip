@@ -411,13 +411,14 @@ __device__ __forceinline__ void stage_store_run(u32x4* st, uint8_t* out, const u
 
 // LDS layout of k_verify: the region bitmap (rw words), a control block of
 // kVerifyCtrlWords words (per-item first-n slots, level counts, the item,
-// phase-clock sums),
-// then the medium primes' (q, S mod q), their current first-hit offsets, and
-// -- when it fits -- the lane-task table.
+// phase-clock sums), then the medium primes' (q, S mod q), their current
+// first-hit offsets, the lane-task table when it fits, and in per-n mode
+// (when it fits) one store-staging area per wave, 16-byte aligned.
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // MODE 0: verify, aggregates only; MODE 1: verify + per-n bytes;
-// MODE 2: Algorithm 1 alone, bitmap to HBM.
+// MODE 2: Algorithm 1 alone, bitmap to HBM.  PH: the phase-clock instance
+// (measurement only).
 template <int MODE, bool PH = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 4 : 8))) void k_verify(Launch L)
 {
