@@ -6,11 +6,13 @@
 //   k_prepare      zero the per-launch accumulators and the work queue
 //   k_bucket       primes above the medium range: every odd multiple of p^2
 //                  that falls in a segment region goes to that segment's hit
-//                  slots (by first hit for p <= 2^20, by cofactor above)
+//                  slots (by first hit up to a cut-over chosen per launch, at
+//                  most 2^20; by cofactor enumeration above it)
 //   k_verify       persistent workgroups pull runs of consecutive segments;
 //                  per segment: Algorithm 1 in LDS, then Algorithm 2 as a
-//                  bit-sliced scan of the LDS bitmap (or, in sieve mode, the
-//                  bitmap streamed to HBM)
+//                  bit-sliced scan of the LDS bitmap (in per-n mode also one
+//                  byte per n to HBM, staged through LDS; in sieve mode the
+//                  bitmap itself to HBM)
 //   k_tail         exact search for the rare n not resolved from LDS
 //   k_finalize     per interval: aggregates, record-setters, exceptions
 #include <type_traits>
