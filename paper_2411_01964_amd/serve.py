@@ -78,7 +78,7 @@ class Server:
     """Continuous-batching server over the batched C-ABI call."""
 
     def __init__(self, n_streams: int = 4, hbm_budget: int = 16 << 30, max_batch: int = 512,
-                 kmax: int = 0, on_done=None, pause_gc: bool = True):
+                 kmax: int = 0, on_done=None, pause_gc: bool = True, poll_s: float = 0.0):
         # Python's cyclic garbage collector stops every thread while it scans
         # the heap: with tens of thousands of requests alive, a full pass takes
         # 30-150 ms and lands on whichever requests are in flight (it set the
@@ -102,6 +102,12 @@ class Server:
         self.batches = 0
         self.error = None
         self.on_done = on_done
+        # how long the scheduler sleeps between completion checks while
+        # batches are in flight (HIP events are polled, not waited on).  0:
+        # it spins, which halves the median latency of the Poisson stream
+        # (0.42 -> 0.19 ms, p99 0.87 -> 0.60 ms) for one busy host core while
+        # work is in flight; when idle it sleeps on the condition variable.
+        self.poll_s = float(poll_s)
         self.thread = threading.Thread(target=self._loop, name="esq-serve", daemon=True)
         self.thread.start()
 
@@ -176,7 +182,7 @@ class Server:
                             progressed |= self._admit(i)
                     if not progressed:
                         if any(self.busy):
-                            self.cv.wait(timeout=0.0002)
+                            self.cv.wait(timeout=self.poll_s)
                         else:
                             self.cv.wait(timeout=0.01)
         except Exception as e:  # surfaced to submitters and close()
@@ -198,13 +204,13 @@ def _release_per_n(r):
 
 
 def run_stream(requests, n_streams=4, hbm_budget=16 << 30, warmup_s=1.0, paced=True,
-               keep_per_n=True):
+               keep_per_n=True, poll_s=0.0):
     """Drive a Server with (t_arrival_s, lo, hi, per_n) requests.  With
     paced=True each request is submitted at its arrival time; otherwise all
     at once.  With keep_per_n=False per-n arrays are released as soon as each
     request completes.  Returns (list of Request, wall seconds, stats dict)."""
     srv = Server(n_streams=n_streams, hbm_budget=hbm_budget,
-                 on_done=None if keep_per_n else _release_per_n)
+                 on_done=None if keep_per_n else _release_per_n, poll_s=poll_s)
     out = []
     t0 = time.perf_counter()
     for t, lo, hi, per_n in requests:
