@@ -210,7 +210,7 @@ int esq_profile_take(double *total_ms, uint64_t *launches);
  * its search (Algorithm 2) or bitmap store, in ticks of the device's
  * constant-rate counter (100 MHz on MI355X).  esq_phase_take waits for the
  * device, writes the three sums to ticks (host, 3 values) and clears them.
- * Returns ESQ_EINVAL for a null pointer or before esq_init.
+ * Returns ESQ_EINVAL for a null pointer, ESQ_ENOINIT before esq_init.
  */
 int esq_phase_take(uint64_t *ticks);
 

@@ -1138,7 +1138,7 @@ int esq_phase_take(uint64_t* ticks)
         return fail(ESQ_EINVAL, "null pointer");
     Ctx* c = g_ctx;
     if (!c)
-        return fail(ESQ_EINVAL, "esq_init has not been called");
+        return fail(ESQ_ENOINIT, "esq_init has not been called");
     hipError_t e;
     if ((e = hipSetDevice(c->device)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess ||
         (e = hipMemcpy(ticks, c->d_phase, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost)) != hipSuccess ||

@@ -52,6 +52,19 @@ def test_calls_before_init_fail_cleanly():
     assert rc == -5
 
 
+def test_measurement_calls_validate_arguments():
+    L = esq.lib()
+    assert L.esq_phase_take(None) == -1          # ESQ_EINVAL
+    assert L.esq_measure_ceilings(None) == -1
+    L.esq_shutdown()
+    out = (ctypes.c_uint64 * 3)()
+    assert L.esq_phase_take(out) == -5           # ESQ_ENOINIT
+    for name, bad in (("sieve_seg_log2", 9), ("sieve_seg_log2", 21), ("phase_clock", 2)):
+        with pytest.raises(esq.EsqError):
+            esq.set_param(name, bad)
+    assert esq.get_param("sieve_seg_log2") == 19 and esq.get_param("phase_clock") == 0
+
+
 def test_param_validation():
     assert esq.get_param("seg_log2") >= 10
     with pytest.raises(esq.EsqError):
