@@ -126,6 +126,16 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _per_n_buffer(n0: int, n_odd: int, dev):
+    """Device bytes for the per-n output of the odd n from n0: a view placed
+    so that its address is congruent to n0's odd index mod 16.  The library
+    writes each wave's 4 KB run of bytes with 16-byte stores from 16-byte
+    boundaries then, without the shifted path for a misaligned run."""
+    buf = torch.empty(max(n_odd, 1) + 16, dtype=torch.uint8, device=dev)
+    off = (((n0 - 1) // 2) - buf.data_ptr()) % 16
+    return buf[off:off + max(n_odd, 1)]
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -209,8 +219,7 @@ class Pending:
         self.exc_cap = int(exceptions_cap)
         self.exceptions = (torch.empty(self.exc_cap, dtype=torch.int64, device=dev)
                            if self.exc_cap else None)
-        self.per_n = (torch.empty(max(self.n_odd, 1), dtype=torch.uint8, device=dev)
-                      if per_n else None)
+        self.per_n = _per_n_buffer(n0, self.n_odd, dev) if per_n else None
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().esq_verify_range(
             self.lo, self.hi, self.kmax, _ptr(self.per_n), _ptr(self.summary),
@@ -329,7 +338,7 @@ class PendingBatch:
                 if per_n[i]:
                     n0 = max(int(self.lo[i]), 3) | 1
                     n_odd = (int(self.hi[i]) - n0 + 1) // 2 if int(self.hi[i]) > n0 else 0
-                    t = torch.empty(max(n_odd, 1), dtype=torch.uint8, device=dev)
+                    t = _per_n_buffer(n0, n_odd, dev)
                     self.per_n.append(t[:n_odd])
                     ptrs[i] = t.data_ptr()
                 else:

@@ -159,9 +159,10 @@ def test_deep_path_crt_construction():
 
 def test_per_n_every_alignment():
     """Per-n bytes of one interval against the oracle, then of the same
-    interval started j odd numbers later (every start mod 16 of the output
-    bytes, and a few more), against the first one shifted by j; with one
-    and with eight waves per workgroup."""
+    interval started j odd numbers later (every start mod 16, and a few
+    more), against the first one shifted by j; with one and with eight waves
+    per workgroup.  (The binding places each output so that its runs start
+    16-byte aligned; the next test covers every other alignment.)"""
     lo, hi = (1 << 40) + 1, (1 << 40) + 1 + (1 << 22)
     knobs()
     base = esq.verify_range(lo, hi, per_n=True)
