@@ -56,6 +56,16 @@ extern "C" {
                                         exception list are incomplete */
 #define ESQ_STATUS_BUCKET_OVERFLOW 2u /* internal bound on large-prime hits
                                          exceeded (never expected) */
+#define ESQ_STATUS_EXCEPTIONS_INCOMPLETE 4u /* kmax <= the in-LDS depth and more
+                                               exceptions than the tail capacity:
+                                               every count is exact, the list of
+                                               exceptions may miss some */
+
+/* esq_record.flags bits */
+#define ESQ_RECORD_KMAX_LIMIT 1u /* k = 0 record: the search stopped at kmax
+                                    while 2^(kmax+1) < n, i.e. a larger k was
+                                    still positive; 0 = every k with 2^k < n
+                                    was tried and failed */
 
 #define ESQ_MAX_HI (((uint64_t)1) << 56) /* largest hi accepted by esq_init */
 #define ESQ_RECORDS_CAP 64               /* capacity of out_records per call */
@@ -64,11 +74,13 @@ extern "C" {
 /* A record-setter (Table 3 of Section 4): an odd n whose least k is strictly
  * larger than the least k of every smaller odd n of the same call.  An n with
  * no representation counts as deeper than any k: it is reported once, with
- * k = 0, and no later n of the call can be a record. */
+ * k = 0, and no later n of the call can be a record.  flags tells why such an
+ * n has none (Algorithm 2's "no representation found" report): the search
+ * limit kmax, or exhaustion of every positive n - 2^k. */
 typedef struct esq_record {
     uint64_t n;
-    uint32_t k;        /* least k, or 0 for an n with no representation */
-    uint32_t reserved; /* 0 */
+    uint32_t k;     /* least k, or 0 for an n with no representation */
+    uint32_t flags; /* ESQ_RECORD_* bits; 0 unless k = 0 */
 } esq_record;
 
 /* Aggregates of one call ("Collecting the results", Section 3; Table 4). */
@@ -146,6 +158,22 @@ int esq_verify_batch(uint32_t count, const uint64_t *lo, const uint64_t *hi, uin
                      esq_record *out_records, void *stream);
 
 /*
+ * Device scratch, in bytes, that one esq_verify_batch call over these
+ * intervals takes from the library's memory pool while it runs: per-segment
+ * hit slots of the large primes, the list of n left to the exact tail pass,
+ * per-interval descriptors and accumulators.  The caller's outputs
+ * (summaries, records, per-n bytes) are not included.  For count = 1 it is
+ * also the scratch of esq_verify_range on that interval with
+ * exceptions_cap = 0.  For admission control by a server: a request is
+ * admitted when its scratch and its outputs fit in device memory.
+ *   count, lo, hi, kmax  as in esq_verify_batch (host arrays)
+ *   out_bytes            host, required
+ * Synchronous; enqueues nothing.  Errors as esq_verify_batch.
+ */
+int esq_scratch_bytes(uint32_t count, const uint64_t *lo, const uint64_t *hi, uint32_t kmax,
+                      uint64_t *out_bytes);
+
+/*
  * Prepared batches: the same work as esq_verify_batch, planned once, with its
  * scratch and descriptors kept on the device, so that it can be launched
  * repeatedly without host planning, allocation or copies -- and captured as
@@ -160,6 +188,9 @@ int esq_verify_batch(uint32_t count, const uint64_t *lo, const uint64_t *hi, uin
  *   esq_batch_destroy  waits for the device and frees the handle.
  */
 typedef struct esq_batch esq_batch;
+/* A prepared batch holds the library's resident tables: esq_batch_launch
+ * returns ESQ_EINVAL, launching nothing, once esq_init has replaced them (a
+ * larger max_hi, another device) or esq_shutdown has released them. */
 int esq_batch_create(uint32_t count, const uint64_t *lo, const uint64_t *hi, uint32_t kmax,
                      uint8_t *const *d_out_mink, esq_summary *out_summaries,
                      esq_record *out_records, esq_batch **out_handle);

@@ -171,9 +171,22 @@ typedef struct {
 
 typedef struct {
     uint64_t n;
-    uint32_t k; /* 0 = exception (depth "infinity") */
-    uint32_t pad;
+    uint32_t k;     /* 0 = exception (depth "infinity") */
+    uint32_t flags; /* k = 0 only: 1 when the search stopped at kmax while a
+                       larger k still gave a positive n - 2^k, 0 when every k
+                       with 2^k < n was tried */
 } oracle_record;
+
+/* Why Algorithm 2 found no representation of n (its "no representation
+ * found" report, Section 3): 1 = the limit kmax cut the search short, i.e.
+ * the next exponent kmax + 1 still has 2^(kmax+1) < n; 0 = the positivity
+ * bound 2^k < n ended it. */
+static uint32_t exception_kind(uint64_t n, unsigned kmax)
+{
+    if (kmax == 0 || kmax >= 63)
+        return 0;
+    return ((uint64_t)1 << (kmax + 1)) < n ? 1u : 0u;
+}
 
 typedef struct {
     /* input */
@@ -209,7 +222,7 @@ static void *chunk_run(void *arg)
         if (depth > depth_max) {
             c->recs[c->nrecs].n = n;
             c->recs[c->nrecs].k = k;
-            c->recs[c->nrecs].pad = depth;
+            c->recs[c->nrecs].flags = k ? 0u : exception_kind(n, c->kmax);
             c->nrecs++;
             depth_max = depth;
         }
@@ -289,12 +302,12 @@ int oracle_verify_range(uint64_t lo, uint64_t hi, unsigned kmax, int nthreads,
         if (ch[t].kmax_seen > sum->kmax_seen)
             sum->kmax_seen = ch[t].kmax_seen;
         for (j = 0; j < ch[t].nrecs; j++) {
-            unsigned depth = ch[t].recs[j].pad;
+            unsigned depth = ch[t].recs[j].k ? ch[t].recs[j].k : 65;
             if (depth > run_max) {
                 if (nrec < rec_cap) {
                     records[nrec].n = ch[t].recs[j].n;
                     records[nrec].k = ch[t].recs[j].k;
-                    records[nrec].pad = 0;
+                    records[nrec].flags = ch[t].recs[j].flags;
                 }
                 nrec++;
                 run_max = depth;

@@ -32,7 +32,7 @@ class _Summary(ctypes.Structure):
 
 
 class _Record(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_uint64), ("k", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+    _fields_ = [("n", ctypes.c_uint64), ("k", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 def build(force: bool = True) -> str:
@@ -153,8 +153,10 @@ def verify_range(lo: int, hi: int, kmax: int = 0, per_n: bool = False,
     Table 4 counts.
 
     Returns a dict: n0, n_odd, hist (65 ints), ksum, kmax_seen, records
-    [(n, k)], n_records, exceptions [n] (ascending, at most exc_cap),
-    n_exceptions, and per_n (uint8 array) when requested.
+    [(n, k)], record_flags (1 for a k = 0 record whose search the limit kmax
+    cut short while 2^(kmax+1) < n, else 0), n_records, exceptions [n]
+    (ascending, at most exc_cap), n_exceptions, and per_n (uint8 array) when
+    requested.
     """
     lib = _load()
     lo, hi = int(lo), int(hi)
@@ -179,6 +181,7 @@ def verify_range(lo: int, hi: int, kmax: int = 0, per_n: bool = False,
         "kmax_seen": int(s.kmax_seen),
         "n_records": int(s.n_records),
         "records": [(int(recs[i].n), int(recs[i].k)) for i in range(nrec)],
+        "record_flags": [int(recs[i].flags) for i in range(nrec)],
         "n_exceptions": int(s.n_exceptions),
         "exceptions": [int(x) for x in exc[:nexc]],
     }

@@ -71,11 +71,13 @@ struct Ctx {
     hipMemPool_t pool = nullptr;    // per-call scratch: stream-ordered, kept cached
     std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
     std::map<std::tuple<int, uint32_t, size_t>, int> occupancy;  // (mode, block, LDS bytes) -> workgroups per CU
+    uint64_t generation = 0;        // changes whenever a device table that a prepared batch holds is replaced
 };
 
 std::mutex g_mu;
 Ctx* g_ctx = nullptr;
 Params g_par;
+uint64_t g_generation = 0;  // under g_mu: last generation handed out
 
 // event pairs recorded around verify-kernel launches while "profile" is on
 std::mutex g_prof_mu;
@@ -245,10 +247,9 @@ uint32_t prime_upper(const Ctx* c, uint64_t x)
 // length S: per prime (q, S mod q), and lane-tasks -- prime i with up to
 // h = ceil(R / q) marks per region is split into c = ceil(h / entry_hits)
 // tasks; task v marks f + (v + c t) q, t >= 0.
-int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_t entry_hits,
-                  MedTable** out)
+int get_med_table_locked(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_t entry_hits,
+                         MedTable** out)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
     const auto key = std::make_tuple(rw, log2S, med_end, entry_hits);
     auto it = c->med.find(key);
     if (it != c->med.end()) {
@@ -308,6 +309,13 @@ int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_
     return ESQ_OK;
 }
 
+int get_med_table(Ctx* c, uint32_t rw, uint32_t log2S, uint32_t med_end, uint32_t entry_hits,
+                  MedTable** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return get_med_table_locked(c, rw, log2S, med_end, entry_hits, out);
+}
+
 uint32_t wheel_base(int64_t region_start)
 {
     const int64_t g = region_start / 64;  // exact, region_start is a multiple of 64
@@ -330,6 +338,28 @@ int snapshot(Ctx** c, Params* par)
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
     return ESQ_OK;
+}
+
+// End of the medium primes for the knobs: primes[kFirstMedium .. end) are the
+// odd primes 17 .. medium_max present in the table.
+uint32_t medium_end(const Ctx* c, const Params& par)
+{
+    uint32_t e = std::max<uint32_t>(kFirstMedium, prime_upper(c, (uint64_t)par.medium_max));
+    return std::min<uint32_t>(e, kFirstMedium + (uint32_t)kMaxMedium);
+}
+
+// The medium-prime tables of the verify geometry for the current knobs, made
+// at set-up (esq_init, esq_set_param; g_mu held) so that calls find them
+// resident.
+int prebuild_med_table(Ctx* c, const Params& par)
+{
+    const uint32_t med_end = medium_end(c, par);
+    if (med_end <= kFirstMedium)
+        return ESQ_OK;
+    const uint32_t hlo = (par.kh >= 7 ? (1u << (par.kh - 1)) : 64u) / 64;
+    const uint32_t rw = hlo + (uint32_t)((1ull << par.seg_log2) / 64);
+    MedTable* mt = nullptr;
+    return get_med_table_locked(c, rw, (uint32_t)par.seg_log2, med_end, (uint32_t)par.entry_hits, &mt);
 }
 
 // One interval to process, in odd-index terms: verify -> the n-indices
@@ -355,7 +385,7 @@ struct Planned {
 
 // Plan one launch over `reqs` (mode 0/1 verify, 2 sieve).
 int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<Req>& reqs,
-         Planned* P)
+         bool exc_list, Planned* P, bool no_alloc = false)
 {
     const uint32_t n_iv = (uint32_t)reqs.size();
     const uint32_t log2S = (uint32_t)(mode == 2 ? par.sieve_seg_log2 : par.seg_log2);
@@ -363,11 +393,14 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     const uint32_t SW = (uint32_t)(S / 64);
     const uint32_t kmax_eff = kmax ? kmax : 63;
     const uint32_t klds = std::min<uint32_t>(kmax_eff, (uint32_t)par.kh);
+    // The halo below a segment holds the candidates of depth up to kh, also
+    // when kmax is smaller (a larger halo is harmless): the geometry, and with
+    // it the medium-prime tables, depends on the knobs only.
     uint32_t hlo = 0, hup = 0;
     if (mode == 2) {
         hup = 1;
     } else {
-        hlo = (klds >= 7 ? (1u << (klds - 1)) : 64u) / 64;
+        hlo = (par.kh >= 7 ? (1u << (par.kh - 1)) : 64u) / 64;
     }
     const uint32_t rw = hlo + SW + hup;
     const uint64_t R = (uint64_t)rw * 64;
@@ -410,10 +443,10 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
         pmax_all = std::max(pmax_all, pmax[i]);
     }
 
-    // medium primes: 17 .. min(medium_max, largest needed)
-    uint32_t med_end = std::max<uint32_t>(kFirstMedium, prime_upper(c, std::min<uint64_t>(
-                                                  (uint64_t)par.medium_max, pmax_all)));
-    med_end = std::min<uint32_t>(med_end, kFirstMedium + (uint32_t)kMaxMedium);
+    // medium primes: 17 .. medium_max, whatever the interval (a prime whose
+    // square exceeds every candidate marks only numbers no n looks at, or
+    // none), so that the tables depend on the knobs only
+    const uint32_t med_end = medium_end(c, par);
     // Bucket primes up to P0 take one first-hit computation (a 64-bit
     // modulo) each; the primes above P0 are found from their cofactors, one
     // thread per odd j <= m_hi / P0^2 (two square roots, mostly an empty range
@@ -493,8 +526,18 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
 
     MedTable* mt = nullptr;
     int rc;
-    if (med_end > kFirstMedium && (rc = get_med_table(c, rw, log2S, med_end, (uint32_t)par.entry_hits, &mt)))
-        return rc;
+    if (med_end > kFirstMedium) {
+        if (no_alloc) {
+            // only a table made at set-up: making one here would allocate
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = c->med.find(std::make_tuple(rw, log2S, med_end, (uint32_t)par.entry_hits));
+            if (it == c->med.end())
+                return fail(ESQ_ENOMEM, "medium-prime tables for these knobs are not resident");
+            mt = &it->second;
+        } else if ((rc = get_med_table(c, rw, log2S, med_end, (uint32_t)par.entry_hits, &mt))) {
+            return rc;
+        }
+    }
 
     uint32_t cap = 0;
     if (any_bucket) {
@@ -558,7 +601,11 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
             }
         n_items = (uint32_t)items.size();
     }
-    const uint64_t tail_cap = mode == 2 ? 1 : std::max<uint64_t>(1, (uint64_t)par.tail_cap);
+    // no tail pass when the search limit is the in-LDS depth: the list then
+    // only holds exceptions, and only when the call lists them
+    const bool no_tail = klds >= kmax_eff;
+    const uint64_t tail_cap = (mode == 2 || (no_tail && !exc_list))
+                                  ? 1 : std::max<uint64_t>(1, (uint64_t)par.tail_cap);
 
     // scratch layout, one allocation
     size_t off = 0;
@@ -598,6 +645,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.stage = stage ? 1u : 0u;
     L.k_lds = mode == 2 ? 0 : klds;
     L.kmax_eff = kmax_eff;
+    L.exc_list = exc_list ? 1u : 0u;
     L.bucket_cap = cap;
     L.nprimes = (uint32_t)c->primes.size();
     L.primes = c->d_primes;
@@ -676,7 +724,7 @@ int enqueue(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vecto
             hipStream_t s)
 {
     Planned P;
-    int rc = plan(c, par, mode, kmax, reqs, &P);
+    int rc = plan(c, par, mode, kmax, reqs, out_exceptions != nullptr, &P);
     if (rc)
         return rc;
     char* base = nullptr;
@@ -735,6 +783,7 @@ struct esq_batch {
     Planned P;
     char* base = nullptr;
     int device = 0;
+    uint64_t generation = 0;  // Ctx::generation of the tables P.L points at
     bool profile = false;
     void* out_summaries = nullptr;
     void* out_records = nullptr;
@@ -764,6 +813,7 @@ int esq_init(int device, uint64_t max_hi)
     if (!g_ctx) {
         g_ctx = new Ctx();
         g_ctx->device = device;
+        g_ctx->generation = ++g_generation;
         fresh = true;
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
@@ -849,8 +899,13 @@ int esq_init(int device, uint64_t max_hi)
         c->primes.swap(pr);
         c->inv_pref.swap(pref);
         c->plimit = need;
+        c->generation = ++g_generation;  // prepared batches hold the old table
     }
     c->max_hi = std::max(c->max_hi, max_hi);
+    // the medium-prime tables of the current knobs (they need the primes)
+    int rc = prebuild_med_table(c, g_par);
+    if (rc)
+        return rc;
     if ((e = hipDeviceSynchronize()) != hipSuccess)
         return hip_fail(e, "hipDeviceSynchronize(init)");
     return ESQ_OK;
@@ -942,6 +997,35 @@ int esq_verify_batch(uint32_t count, const uint64_t* lo, const uint64_t* hi, uin
                    (hipStream_t)stream);
 }
 
+int esq_scratch_bytes(uint32_t count, const uint64_t* lo, const uint64_t* hi, uint32_t kmax,
+                      uint64_t* out_bytes)
+{
+    t_err.clear();
+    if (!out_bytes)
+        return fail(ESQ_EINVAL, "out_bytes is null");
+    *out_bytes = 0;
+    Ctx* c;
+    Params par;
+    int rc = snapshot(&c, &par);
+    if (rc)
+        return rc;
+    if (count == 0)
+        return ESQ_OK;
+    if (!lo || !hi)
+        return fail(ESQ_EINVAL, "null lo or hi");
+    if (kmax > 63)
+        return fail(ESQ_EINVAL, "kmax > 63");
+    std::vector<Req> reqs;
+    bool per_n = false;
+    if ((rc = make_batch_reqs(c, count, lo, hi, nullptr, &reqs, &per_n)))
+        return rc;
+    Planned P;
+    if ((rc = plan(c, par, 0, kmax, reqs, false, &P)))
+        return rc;
+    *out_bytes = P.bytes;
+    return ESQ_OK;
+}
+
 int esq_batch_create(uint32_t count, const uint64_t* lo, const uint64_t* hi, uint32_t kmax,
                      uint8_t* const* d_out_mink, esq_summary* out_summaries,
                      esq_record* out_records, esq_batch** out_handle)
@@ -968,7 +1052,8 @@ int esq_batch_create(uint32_t count, const uint64_t* lo, const uint64_t* hi, uin
     b->profile = par.profile != 0;
     b->out_summaries = out_summaries;
     b->out_records = out_records;
-    if ((rc = plan(c, par, per_n ? 1 : 0, kmax, reqs, &b->P))) {
+    b->generation = c->generation;
+    if ((rc = plan(c, par, per_n ? 1 : 0, kmax, reqs, false, &b->P))) {
         delete b;
         return rc;
     }
@@ -996,6 +1081,14 @@ int esq_batch_launch(esq_batch* b, int use_graph, void* stream)
     t_err.clear();
     if (!b)
         return fail(ESQ_EINVAL, "null batch");
+    {
+        // the batch's launch points at the context's prime, wheel and
+        // medium-prime tables: they must still be the ones it was planned on
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_ctx || g_ctx->device != b->device || g_ctx->generation != b->generation)
+            return fail(ESQ_EINVAL, "prepared batch is stale: esq_init or esq_shutdown has replaced "
+                                    "the tables it was planned on (destroy it and create it again)");
+    }
     hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
@@ -1106,6 +1199,12 @@ int esq_set_param(const char* name, int64_t value)
         g_par.runs_per_wg = value;
     } else {
         return fail(ESQ_EINVAL, "unknown parameter " + n);
+    }
+    if (g_ctx && (n == "seg_log2" || n == "kh" || n == "medium_max" || n == "entry_hits")) {
+        hipError_t e = hipSetDevice(g_ctx->device);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipSetDevice");
+        return prebuild_med_table(g_ctx, g_par);
     }
     return ESQ_OK;
 }

@@ -77,7 +77,8 @@ struct Launch {
     uint32_t mode;                // 0 verify, 1 verify + per-n, 2 sieve
     uint32_t med_end;             // medium primes primes[kFirstMedium .. med_end)
     uint32_t n_tasks;
-    uint32_t k_lds, kmax_eff;
+    uint32_t k_lds, kmax_eff;     // k_lds >= kmax_eff: every n unresolved in LDS is an exception
+    uint32_t exc_list;            // 1: the call lists its exceptions (single interval)
     uint32_t bucket_cap;          // hit slots per segment
     uint32_t nprimes;
     const Interval* iv;

@@ -858,8 +858,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 }
                 // the loop ends early (alive false) for all but the rarest words
                 const uint64_t U = ((uint64_t)uhi << 32) | ulo;
-                if (__builtin_expect(alive, 0) && U) {
-                    // still unresolved after the in-LDS steps: exact tail pass
+                // still unresolved after the in-LDS steps: to the exact tail
+                // pass -- unless the search limit is the in-LDS depth, so that
+                // these n are exceptions already counted in cnt[k_lds]; then
+                // they are listed only when the call lists exceptions
+                const bool no_tail = klds >= L.kmax_eff;
+                if (__builtin_expect(alive, 0) && U && (!no_tail || L.exc_list)) {
                     // one reservation of popcount(U) list entries per word
                     const uint64_t j0 = j0_of();
                     const unsigned long long c = (unsigned long long)__popcll(U);
@@ -872,7 +876,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                             L.tail_n[idx] = j0 + (uint64_t)bit;
                             L.tail_iv[idx] = ivi;
                         } else {
-                            atomicOr(&IV.acc->status, (unsigned)ESQ_STATUS_TAIL_OVERFLOW);
+                            atomicOr(&IV.acc->status, no_tail ? (unsigned)ESQ_STATUS_EXCEPTIONS_INCOMPLETE
+                                                              : (unsigned)ESQ_STATUS_TAIL_OVERFLOW);
                         }
                     }
                 }
@@ -995,6 +1000,13 @@ __global__ __launch_bounds__(256) void k_tail(Launch L)
     volatile int* hitp = &s_hit;
     for (uint64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const uint64_t j = L.tail_n[idx];
+        if (L.k_lds >= L.kmax_eff) {
+            // listed exceptions: no k is left to try, and the counts, first-n
+            // slots and per-n bytes are complete already
+            if (threadIdx.x == 0)
+                L.tail_d[idx] = 0;
+            continue;
+        }
         const Interval IV = L.iv[L.tail_iv[idx]];
         const uint64_t n = 2 * j + 1;
         uint32_t d = 0;
@@ -1076,10 +1088,14 @@ __global__ __launch_bounds__(1024) void k_finalize(Launch L, void* out_summaries
     const unsigned long long tail_total = *L.tail_count;
     const uint64_t nlist = tail_total < L.tail_cap ? tail_total : L.tail_cap;
     const uint64_t n_odd = IV.I1 - IV.I0;
-    const uint64_t n_exc = A->deep_hist[0];
+    // with the search limit at the in-LDS depth there is no tail pass: the n
+    // still unresolved after step k_lds are the exceptions, and they are
+    // deeper than every level, so first[k] for k > k_lds + 1 is first[k_lds + 1]
+    const bool no_tail = L.k_lds >= L.kmax_eff;
+    const uint64_t n_exc = no_tail ? A->cnt[L.k_lds] : A->deep_hist[0];
     const uint64_t want = n_exc < exc_cap ? n_exc : exc_cap;
     for (uint32_t i = tid; i < 65; i += T)
-        s_first[i] = A->first[i];
+        s_first[i] = (no_tail && i > L.k_lds + 1) ? A->first[L.k_lds + 1] : A->first[i];
 
     if (out_exceptions && want > 0) {
         // the want-th smallest exception of this interval (binary search on
@@ -1140,7 +1156,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Launch L, void* out_summaries
     __shared__ unsigned long long h[65];
     __shared__ unsigned long long s_cnt[16];
     for (uint32_t i = tid; i < 65; i += T)
-        h[i] = A->deep_hist[i];
+        h[i] = no_tail ? (i == 0 ? n_exc : 0ull) : A->deep_hist[i];
     for (uint32_t i = tid; i < 16; i += T)
         s_cnt[i] = A->cnt[i];
     __syncthreads();
@@ -1175,9 +1191,13 @@ __global__ __launch_bounds__(1024) void k_finalize(Launch L, void* out_summaries
             while (kk < 64 && s_first[kk + 1] == v)
                 kk++;
             if (rec && nrec < ESQ_RECORDS_CAP) {
-                rec[nrec].n = 2 * v + 1;
+                const uint64_t n = 2 * v + 1;
+                rec[nrec].n = n;
                 rec[nrec].k = kk == 64 ? 0u : kk;
-                rec[nrec].reserved = 0;
+                // an exception found by the search limit, with a larger k
+                // still positive, vs one for which every k with 2^k < n failed
+                rec[nrec].flags = (kk == 64 && L.kmax_eff < 63 && (1ull << (L.kmax_eff + 1)) < n)
+                                      ? (uint32_t)ESQ_RECORD_KMAX_LIMIT : 0u;
             }
             nrec++;
             k = kk + 1;

@@ -21,10 +21,13 @@ ESQ_EXCEPTIONS_CAP_MAX = 16384
 ESQ_MAX_HI = 1 << 56
 STATUS_TAIL_OVERFLOW = 1
 STATUS_BUCKET_OVERFLOW = 2
+STATUS_EXCEPTIONS_INCOMPLETE = 4
+RECORD_KMAX_LIMIT = 1
 
 # every function declared in include/esq.h
 EXPORTS = ("esq_init", "esq_sieve_segment", "esq_verify_range", "esq_verify_batch",
            "esq_batch_create", "esq_batch_launch", "esq_batch_destroy",
+           "esq_scratch_bytes",
            "esq_set_param", "esq_get_param", "esq_profile_take", "esq_phase_take",
            "esq_measure_ceilings",
            "esq_last_error", "esq_shutdown")
@@ -45,7 +48,7 @@ class Summary(ctypes.Structure):
 
 
 class Record(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_uint64), ("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+    _fields_ = [("n", ctypes.c_uint64), ("k", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 SUMMARY_BYTES = ctypes.sizeof(Summary)
@@ -57,7 +60,7 @@ def _np_dtypes():
     summary = np.dtype([("n0", "<u8"), ("n_odd", "<u8"), ("hist", "<u8", 65), ("ksum", "<u8"),
                         ("kmax_seen", "<u4"), ("n_records", "<u4"), ("n_exceptions", "<u8"),
                         ("status", "<u4"), ("reserved", "<u4")])
-    record = np.dtype([("n", "<u8"), ("k", "<u4"), ("reserved", "<u4")])
+    record = np.dtype([("n", "<u8"), ("k", "<u4"), ("flags", "<u4")])
     assert summary.itemsize == SUMMARY_BYTES and record.itemsize == RECORD_BYTES
     return summary, record
 
@@ -99,6 +102,8 @@ def lib():
         L.esq_batch_launch.restype = ctypes.c_int
         L.esq_batch_destroy.argtypes = [vp]
         L.esq_batch_destroy.restype = None
+        L.esq_scratch_bytes.argtypes = [u32, vp, vp, u32, ctypes.POINTER(u64)]
+        L.esq_scratch_bytes.restype = ctypes.c_int
         L.esq_set_param.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         L.esq_set_param.restype = ctypes.c_int
         L.esq_get_param.argtypes = [ctypes.c_char_p]
@@ -158,6 +163,19 @@ def set_param(name: str, value: int):
 
 def get_param(name: str) -> int:
     return int(lib().esq_get_param(name.encode()))
+
+
+def scratch_bytes(los, his, kmax: int = 0) -> int:
+    """Device scratch (bytes) that one esq_verify_batch call over these
+    intervals takes from the library's pool while it runs (esq_scratch_bytes);
+    the caller's outputs are not included."""
+    import numpy as np
+    lo = np.ascontiguousarray(np.asarray(los, dtype=np.uint64))
+    hi = np.ascontiguousarray(np.asarray(his, dtype=np.uint64))
+    out = ctypes.c_uint64(0)
+    _check(lib().esq_scratch_bytes(int(lo.size), ctypes.c_void_p(lo.ctypes.data),
+                                   ctypes.c_void_p(hi.ctypes.data), int(kmax), ctypes.byref(out)))
+    return int(out.value)
 
 
 def profile_take():
@@ -236,10 +254,11 @@ class Pending:
         s = Summary.from_buffer_copy(bytes(self.summary.cpu().numpy().tobytes()))
         recs_raw = self.records.cpu().numpy().tobytes()
         nrec = min(s.n_records, ESQ_RECORDS_CAP)
-        recs = []
+        recs, flags = [], []
         for i in range(nrec):
             r = Record.from_buffer_copy(recs_raw[i * RECORD_BYTES:(i + 1) * RECORD_BYTES])
             recs.append((int(r.n), int(r.k)))
+            flags.append(int(r.flags))
         nexc = min(int(s.n_exceptions), self.exc_cap)
         exc = [int(x) for x in self.exceptions[:nexc].cpu().tolist()] if nexc else []
         out = {
@@ -250,6 +269,7 @@ class Pending:
             "kmax_seen": int(s.kmax_seen),
             "n_records": int(s.n_records),
             "records": recs,
+            "record_flags": flags,
             "n_exceptions": int(s.n_exceptions),
             "exceptions": exc,
             "status": int(s.status),
@@ -276,10 +296,11 @@ def verify_range(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None, che
 def _parse(summary_bytes, record_bytes):
     s = Summary.from_buffer_copy(summary_bytes)
     nrec = min(s.n_records, ESQ_RECORDS_CAP)
-    recs = []
+    recs, flags = [], []
     for i in range(nrec):
         r = Record.from_buffer_copy(record_bytes[i * RECORD_BYTES:(i + 1) * RECORD_BYTES])
         recs.append((int(r.n), int(r.k)))
+        flags.append(int(r.flags))
     return {
         "n0": int(s.n0),
         "n_odd": int(s.n_odd),
@@ -288,6 +309,7 @@ def _parse(summary_bytes, record_bytes):
         "kmax_seen": int(s.kmax_seen),
         "n_records": int(s.n_records),
         "records": recs,
+        "record_flags": flags,
         "n_exceptions": int(s.n_exceptions),
         "status": int(s.status),
     }
@@ -301,7 +323,7 @@ def _parse_many(summaries, records, count):
     hist = sm["hist"].tolist()
     cols = {k: sm[k].tolist() for k in ("n0", "n_odd", "ksum", "kmax_seen", "n_records",
                                          "n_exceptions", "status")}
-    rn, rk = rc["n"].tolist(), rc["k"].tolist()
+    rn, rk, rf = rc["n"].tolist(), rc["k"].tolist(), rc["flags"].tolist()
     out = []
     for i in range(count):
         nrec = min(cols["n_records"][i], ESQ_RECORDS_CAP)
@@ -310,6 +332,7 @@ def _parse_many(summaries, records, count):
             "ksum": cols["ksum"][i], "kmax_seen": cols["kmax_seen"][i],
             "n_records": cols["n_records"][i],
             "records": list(zip(rn[i][:nrec], rk[i][:nrec])),
+            "record_flags": rf[i][:nrec],
             "n_exceptions": cols["n_exceptions"][i], "status": cols["status"][i],
         })
     return out

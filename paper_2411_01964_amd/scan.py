@@ -8,10 +8,14 @@ the record-setters of the union are the strict prefix maxima of the
 concatenated record lists (an n without representation counting as deeper
 than any k), and exceptions concatenate.
 
-Checkpoint: one JSON line per finished chunk, {"lo", "hi", "summary", "crc"},
-where crc is the CRC-32 of the summary's canonical JSON.  On resume, lines
-are read in order while they are intact, contiguous and checksummed; the
-rest is recomputed.  A chunk whose verification raises is retried.
+Checkpoint: one JSON line per finished chunk, {"scan_lo", "kmax", "lo", "hi",
+"summary", "crc"}, where crc is the CRC-32 of the line's canonical JSON
+without it.  On resume, lines are read in order while they are intact,
+contiguous and checksummed; the rest of [lo, hi) is cut into chunks again
+from the end of the last intact line, so a resumed scan may use another chunk
+size or a larger hi.  A checkpoint of another scan (a different start or
+kmax, or one reaching past hi) is rejected.  A chunk whose verification
+raises is retried.
 """
 from __future__ import annotations
 
@@ -64,7 +68,17 @@ def _canon(summary):
     return json.dumps(keep, sort_keys=True, separators=(",", ":"))
 
 
-def _read_checkpoint(path, lo):
+def _line(scan_lo, kmax, a, b, s):
+    body = {"scan_lo": scan_lo, "kmax": kmax, "lo": a, "hi": b, "summary": json.loads(_canon(s))}
+    crc = zlib.crc32(json.dumps(body, sort_keys=True, separators=(",", ":")).encode())
+    body["crc"] = crc
+    return json.dumps(body) + "\n"
+
+
+def _read_checkpoint(path, lo, hi, kmax):
+    """The intact, contiguous prefix of a checkpoint of the scan of [lo, ...)
+    with this kmax, as [(a, b, summary)]; raises ValueError for a checkpoint
+    of another scan."""
     done = []
     if not path or not os.path.exists(path):
         return done
@@ -73,15 +87,31 @@ def _read_checkpoint(path, lo):
         for line in f:
             try:
                 rec = json.loads(line)
-                s = rec["summary"]
-                if zlib.crc32(_canon(s).encode()) != rec["crc"] or rec["lo"] != expect:
+                crc = rec.pop("crc")
+                if zlib.crc32(json.dumps(rec, sort_keys=True, separators=(",", ":")).encode()) != crc:
                     break
-            except (ValueError, KeyError, TypeError):
+                s = rec["summary"]
+                a, b = int(rec["lo"]), int(rec["hi"])
+            except (ValueError, KeyError, TypeError, AttributeError):
                 break
+            if rec.get("scan_lo") != lo or rec.get("kmax") != kmax:
+                raise ValueError("checkpoint %s belongs to another scan (start %r, kmax %r; this "
+                                 "scan: start %d, kmax %d)" % (path, rec.get("scan_lo"), rec.get("kmax"),
+                                                                lo, kmax))
+            if a != expect or b <= a:
+                break
+            if b > hi:
+                raise ValueError("checkpoint %s reaches %d, past the end %d of this scan" % (path, b, hi))
             s["records"] = [tuple(r) for r in s["records"]]
-            done.append((rec["lo"], rec["hi"], s))
-            expect = rec["hi"]
+            done.append((a, b, s))
+            expect = b
     return done
+
+
+def odd_count(lo, hi):
+    """Number of odd n >= 3 in [lo, hi)."""
+    n0 = max(int(lo), 3) | 1
+    return (int(hi) - n0 + 1) // 2 if int(hi) > n0 else 0
 
 
 def _gpu_verify_async(kmax, exceptions_cap):
@@ -103,23 +133,23 @@ def scan(lo, hi, chunk=1 << 40, checkpoint=None, kmax=0, exceptions_cap=1024,
     Returns the merged summary."""
     if verify_async is None:
         verify_async = _gpu_verify_async(kmax, exceptions_cap)
-    bounds = []
-    a = lo
-    while a < hi:
-        b = min(hi, a + chunk)
-        bounds.append((a, b))
-        a = b
-    done = _read_checkpoint(checkpoint, lo)
+    lo, hi, kmax = int(lo), int(hi), int(kmax)
+    done = _read_checkpoint(checkpoint, lo, hi, kmax)
     total = empty()
     for _, _, s in done:
         total = merge(total, s)
-    todo = bounds[len(done):]
+    # the rest of the range, cut from the end of the intact prefix
+    todo = []
+    a = done[-1][1] if done else lo
+    while a < hi:
+        b = min(hi, a + chunk)
+        todo.append((a, b))
+        a = b
     if checkpoint:
         # rewrite the intact prefix so that a damaged tail is dropped
         with open(checkpoint + ".tmp", "w") as f:
             for a, b, s in done:
-                f.write(json.dumps({"lo": a, "hi": b, "summary": json.loads(_canon(s)),
-                                    "crc": zlib.crc32(_canon(s).encode())}) + "\n")
+                f.write(_line(lo, kmax, a, b, s))
         os.replace(checkpoint + ".tmp", checkpoint)
     out = open(checkpoint, "a") if checkpoint else None
     try:
@@ -141,8 +171,7 @@ def scan(lo, hi, chunk=1 << 40, checkpoint=None, kmax=0, exceptions_cap=1024,
                 s = _pick(s)
                 total = merge(total, s)
                 if out:
-                    out.write(json.dumps({"lo": a, "hi": b, "summary": json.loads(_canon(s)),
-                                          "crc": zlib.crc32(_canon(s).encode())}) + "\n")
+                    out.write(_line(lo, kmax, a, b, s))
                     out.flush()
                 if progress:
                     progress(a, b, total)
@@ -150,4 +179,7 @@ def scan(lo, hi, chunk=1 << 40, checkpoint=None, kmax=0, exceptions_cap=1024,
     finally:
         if out:
             out.close()
+    if total["n_odd"] != odd_count(lo, hi):
+        raise RuntimeError("merged scan covers %d odd n, [%d, %d) has %d"
+                           % (total["n_odd"], lo, hi, odd_count(lo, hi)))
     return total

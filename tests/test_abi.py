@@ -33,13 +33,15 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "esq.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(esq_summary), sizeof(esq_record),'
-        ' offsetof(esq_summary, ksum), offsetof(esq_summary, status), offsetof(esq_record, k));return 0;}\n')
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(esq_summary), sizeof(esq_record),'
+        ' offsetof(esq_summary, ksum), offsetof(esq_summary, status), offsetof(esq_record, k),'
+        ' offsetof(esq_record, flags));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(esq.Summary), ctypes.sizeof(esq.Record),
-                   esq.Summary.ksum.offset, esq.Summary.status.offset, esq.Record.k.offset]
+                   esq.Summary.ksum.offset, esq.Summary.status.offset, esq.Record.k.offset,
+                   esq.Record.flags.offset]
 
 
 def test_calls_before_init_fail_cleanly():
@@ -50,6 +52,11 @@ def test_calls_before_init_fail_cleanly():
     assert b"esq_init" in L.esq_last_error()
     rc = L.esq_sieve_segment(1, 100, None, None)
     assert rc == -5
+    lo = (ctypes.c_uint64 * 1)(3)
+    hi = (ctypes.c_uint64 * 1)(1001)
+    out = ctypes.c_uint64(7)
+    assert L.esq_scratch_bytes(1, lo, hi, 0, ctypes.byref(out)) == -5
+    assert L.esq_scratch_bytes(1, lo, hi, 0, None) == -1   # ESQ_EINVAL
 
 
 def test_measurement_calls_validate_arguments():

@@ -23,7 +23,8 @@ def lib_ready():
         esq.set_param(k, v)
 
 
-KEYS = ("n0", "n_odd", "hist", "ksum", "kmax_seen", "records", "n_records", "n_exceptions")
+KEYS = ("n0", "n_odd", "hist", "ksum", "kmax_seen", "records", "record_flags", "n_records",
+        "n_exceptions")
 
 
 def same(a, b):
@@ -114,3 +115,47 @@ def test_prepared_batch_and_graph_replays():
                 same(r, eager[i])
     finally:
         pb.close()
+
+
+def test_stale_prepared_batch_is_refused():
+    """A prepared batch holds the library's resident tables: after esq_init
+    replaces them (a larger max_hi) its launch is refused before anything is
+    enqueued, and a batch prepared afterwards runs."""
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+    lo, hi = mixed_intervals(46, 8, log2_len=(8, 12))
+    eager = esq.verify_batch(lo, hi)
+    pb = esq.PreparedBatch(lo, hi)
+    try:
+        pb.launch(graph=True)
+        for i, r in enumerate(pb.results()):
+            same(r, eager[i])
+        esq.init(0, (1 << 52) + 1)             # extends the prime table
+        with pytest.raises(esq.EsqError) as ei:
+            pb.launch(graph=True)
+        assert ei.value.code == -1 and "stale" in str(ei.value)
+    finally:
+        pb.close()
+    pb = esq.PreparedBatch(lo, hi)
+    try:
+        pb.launch(graph=True)
+        for i, r in enumerate(pb.results()):
+            same(r, eager[i])
+    finally:
+        pb.close()
+
+
+def test_scratch_bytes_reports_the_plan():
+    """esq_scratch_bytes: the library's scratch for a batch grows with the
+    segments it covers and with a listed tail; empty batches take none."""
+    for k, v in DEFAULTS.items():
+        esq.set_param(k, v)
+    assert esq.scratch_bytes([], []) == 0
+    small = esq.scratch_bytes([(1 << 40) + 1], [(1 << 40) + (1 << 20)])
+    large = esq.scratch_bytes([(1 << 40) + 1], [(1 << 40) + (1 << 34)])
+    assert 0 < small < large
+    lo, hi = workloads.batch_intervals(seed=4, count=64)
+    assert esq.scratch_bytes(lo, hi) >= max(esq.scratch_bytes([a], [b]) for a, b in zip(lo, hi)) // 2
+    # kmax at or below the in-LDS depth: no tail list
+    assert esq.scratch_bytes([(1 << 40) + 1], [(1 << 40) + (1 << 30)], kmax=3) < \
+        esq.scratch_bytes([(1 << 40) + 1], [(1 << 40) + (1 << 30)])

@@ -42,6 +42,7 @@ def assert_same(g, o, per_n=True):
     assert g["ksum"] == o["ksum"]
     assert g["kmax_seen"] == o["kmax_seen"]
     assert g["records"] == o["records"]
+    assert g["record_flags"] == o["record_flags"]
     assert g["n_records"] == o["n_records"]
     assert g["n_exceptions"] == o["n_exceptions"]
     if "exceptions" in g and g["exceptions"]:
@@ -294,3 +295,30 @@ def test_near_the_largest_supported_n():
         om0, on, ow = oracle.sieve_bits(lo, hi)
         assert (m0, n) == (om0, on)
         assert np.array_equal(words_np(w), ow)
+
+
+@pytest.mark.parametrize("kmax", [1, 3])
+def test_kmax_at_most_kh_needs_no_tail_list(kmax):
+    """With the search limit at or below the in-LDS depth, the n left after
+    the LDS steps are exceptions already counted: a tail list far smaller
+    than their number changes nothing in the counts, records (with their
+    exception kind) or per-n bytes; a listed exception set that did not fit
+    is reported as incomplete, never as wrong."""
+    knobs(tail_cap=1 << 12)
+    lo, hi = 3, (1 << 19) + 1
+    o = oracle.verify_range(lo, hi, kmax=kmax, per_n=True, exc_cap=1 << 20)
+    assert o["n_exceptions"] > 4 * (1 << 12)
+    g = esq.verify_range(lo, hi, kmax=kmax, per_n=True)
+    assert g["status"] == 0
+    assert_same(g, o)
+    assert g["records"][-1][1] == 0 and g["record_flags"][-1] == esq.RECORD_KMAX_LIMIT
+    s = esq.verify_range(lo, hi, kmax=kmax)
+    assert s["hist"] == o["hist"] and s["records"] == o["records"] and s["status"] == 0
+    e = esq.verify_range(lo, hi, kmax=kmax, exceptions_cap=64, check=False)
+    assert e["status"] in (0, esq.STATUS_EXCEPTIONS_INCOMPLETE)
+    assert e["hist"] == o["hist"] and e["records"] == o["records"]
+    if e["status"] == 0:
+        assert e["exceptions"] == o["exceptions"][:64]
+    knobs()
+    e = esq.verify_range(lo, hi, kmax=kmax, exceptions_cap=64)
+    assert e["exceptions"] == o["exceptions"][:64]

@@ -16,7 +16,8 @@ def lib_ready():
         esq.set_param(k, v)
 
 
-KEYS = ("n0", "n_odd", "hist", "ksum", "kmax_seen", "records", "n_records", "n_exceptions")
+KEYS = ("n0", "n_odd", "hist", "ksum", "kmax_seen", "records", "record_flags", "n_records",
+        "n_exceptions")
 
 
 @pytest.mark.parametrize("paced,budget", [(True, 16 << 30), (False, 64 << 20)])

@@ -283,3 +283,32 @@ def test_empty_and_degenerate_ranges():
         assert r["n_odd"] == 0 and sum(r["hist"]) == 0 and r["records"] == []
     r = oracle.verify_range(0, 4)
     assert r["n_odd"] == 1 and r["records"] == [(3, 1)]
+
+
+@pytest.mark.parametrize("kmax", [0, 1, 2, 3])
+def test_aggregates_against_brute_force_below_6000(kmax):
+    """The oracle's per-k counts, sum of k, maximum k, records (with the
+    exception kind) and exceptions over the odd n in [3, 6000), against the
+    same aggregates built here from the all-divisor brute force, n by n
+    (Section 3, "Collecting the results"; Algorithm 2's report)."""
+    r = oracle.verify_range(0, 6000, kmax=kmax, exc_cap=1 << 12)
+    hist, ksum, kseen, recs, flags, exc, best = [0] * 65, 0, 0, [], [], [], 0
+    for n in range(3, 6000, 2):
+        k = brute_mink(n, kmax)
+        hist[k] += 1
+        ksum += k
+        kseen = max(kseen, k)
+        depth = k if k else 1000
+        if depth > best:
+            recs.append((n, k))
+            flags.append(1 if k == 0 and kmax and (1 << (kmax + 1)) < n else 0)
+            best = depth
+        if k == 0:
+            exc.append(n)
+    assert r["hist"] == hist
+    assert r["ksum"] == ksum and r["kmax_seen"] == kseen
+    assert r["records"] == recs and r["record_flags"] == flags
+    assert r["exceptions"] == exc and r["n_exceptions"] == len(exc)
+    if kmax:
+        # the first n deeper than kmax is an exception cut short by the limit
+        assert recs[-1][1] == 0 and flags[-1] == 1

@@ -87,3 +87,29 @@ def test_record_merge_with_exceptions_counts_them_deepest():
     m = scan.merge(scan.merge(a, b), c)
     assert m["records"] == [(3, 1), (11, 2), (29, 0)]
     assert m["exceptions"] == [29] and m["kmax_seen"] == 9
+
+
+def test_resume_with_another_chunk_size_and_a_larger_end(tmp_path):
+    """A scan resumed with a different chunk size and a larger hi continues
+    from the end of the intact checkpoint: nothing skipped, nothing twice."""
+    ck = str(tmp_path / "scan.jsonl")
+    lo = 3
+    scan.scan(lo, lo + 9000, chunk=3000, checkpoint=ck, verify_async=oracle_async())
+    calls = []
+    got = scan.scan(lo, 40000, chunk=6000, checkpoint=ck, verify_async=oracle_async(calls=calls))
+    whole = oracle.verify_range(lo, 40000)
+    for k in KEYS:
+        assert got[k] == whole[k], k
+    assert got["n_odd"] == 19999
+    assert calls[0] == (lo + 9000, lo + 9000 + 6000)
+
+
+def test_checkpoint_of_another_scan_is_rejected(tmp_path):
+    ck = str(tmp_path / "scan.jsonl")
+    scan.scan(3, 9003, chunk=3000, checkpoint=ck, verify_async=oracle_async())
+    with pytest.raises(ValueError, match="another scan"):
+        scan.scan(3, 20000, chunk=3000, checkpoint=ck, kmax=2, verify_async=oracle_async(kmax=2))
+    with pytest.raises(ValueError, match="another scan"):
+        scan.scan(5, 20000, chunk=3000, checkpoint=ck, verify_async=oracle_async())
+    with pytest.raises(ValueError, match="past the end"):
+        scan.scan(3, 5000, chunk=3000, checkpoint=ck, verify_async=oracle_async())
