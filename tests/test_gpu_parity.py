@@ -304,10 +304,11 @@ def test_kmax_at_most_kh_needs_no_tail_list(kmax):
     than their number changes nothing in the counts, records (with their
     exception kind) or per-n bytes; a listed exception set that did not fit
     is reported as incomplete, never as wrong."""
-    knobs(tail_cap=1 << 12)
+    cap = 1 << 12 if kmax == 1 else 1 << 6
+    knobs(tail_cap=cap)
     lo, hi = 3, (1 << 19) + 1
     o = oracle.verify_range(lo, hi, kmax=kmax, per_n=True, exc_cap=1 << 20)
-    assert o["n_exceptions"] > 4 * (1 << 12)
+    assert o["n_exceptions"] > 4 * cap
     g = esq.verify_range(lo, hi, kmax=kmax, per_n=True)
     assert g["status"] == 0
     assert_same(g, o)
