@@ -70,6 +70,8 @@ extern "C" {
 #define ESQ_MAX_HI (((uint64_t)1) << 56) /* largest hi accepted by esq_init */
 #define ESQ_RECORDS_CAP 64               /* capacity of out_records per call */
 #define ESQ_EXCEPTIONS_CAP_MAX 16384     /* largest exceptions_cap accepted */
+#define ESQ_NOALLOC_SCRATCH_MAX (((uint64_t)64) << 20) /* static scratch of
+                                    esq_verify_range_noalloc, per device */
 
 /* A record-setter (Table 3 of Section 4): an odd n whose least k is strictly
  * larger than the least k of every smaller odd n of the same call.  An n with
@@ -136,6 +138,29 @@ int esq_sieve_segment(uint64_t lo, uint64_t hi, uint64_t *d_bits, void *stream);
 int esq_verify_range(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t *d_out_mink,
                      esq_summary *out_summary, esq_record *out_records,
                      uint64_t *out_exceptions, uint64_t exceptions_cap, void *stream);
+
+/*
+ * esq_verify_range for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as esq_verify_range; the
+ * call allocates nothing (no hipMalloc/hipFree, no memory pool, no staging
+ * buffer, no event).  Its scratch (per-interval accumulators, large-prime
+ * hit slots, the list of n left to the exact tail pass) is a static device
+ * array of ESQ_NOALLOC_SCRATCH_MAX bytes that every device the library runs
+ * on holds from esq_init until the process ends.
+ *   - Returns ESQ_ERANGE, enqueuing nothing, when the interval needs more
+ *     scratch than that (esq_scratch_bytes with count = 1 gives the figure;
+ *     about 26 MB for 2^33 odd n near 2^50 with the default knobs), and
+ *     ESQ_ENOMEM when the medium-prime tables of the current knobs are not
+ *     resident (esq_init and esq_set_param make them).
+ *   - Every call on one device uses the same array and clears what must
+ *     start at zero on the device: calls that overlap in time on one device
+ *     (different streams, or threads) race and give wrong results.  Serialise
+ *     them, e.g. on one stream.
+ */
+int esq_verify_range_noalloc(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t *d_out_mink,
+                             esq_summary *out_summary, esq_record *out_records,
+                             uint64_t *out_exceptions, uint64_t exceptions_cap, void *stream);
 
 /*
  * Many intervals in one launch (the batched form of esq_verify_range): every

@@ -20,7 +20,17 @@
 
 using namespace esq;
 
+// Device scratch of esq_verify_range_noalloc: a static array that every
+// device holds from the library's load until the process ends.  In host code
+// the name is a host-side stand-in, never a device address: host code uses
+// the address that hipGetSymbolAddress gives per device at esq_init
+// (g_scratch_ptr), never the name itself.
+static __device__ __align__(256) char scratch[ESQ_NOALLOC_SCRATCH_MAX];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+char* g_scratch_ptr[kMaxDevices];  // under g_mu: device address of `scratch` per device
 
 thread_local std::string t_err;
 
@@ -775,6 +785,38 @@ int make_batch_reqs(const Ctx* c, uint32_t count, const uint64_t* lo, const uint
     return ESQ_OK;
 }
 
+// Argument checks and the single request of esq_verify_range and its
+// no-alloc variant.
+int verify_range_args(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t* d_out_mink,
+                      esq_summary* out_summary, uint64_t* out_exceptions, uint64_t exceptions_cap,
+                      Ctx** c, Params* par, std::vector<Req>* reqs)
+{
+    int rc = snapshot(c, par);
+    if (rc)
+        return rc;
+    if (!out_summary)
+        return fail(ESQ_EINVAL, "out_summary is null");
+    if (kmax > 63)
+        return fail(ESQ_EINVAL, "kmax > 63");
+    if (lo > hi)
+        return fail(ESQ_EINVAL, "lo > hi");
+    if (exceptions_cap > ESQ_EXCEPTIONS_CAP_MAX)
+        return fail(ESQ_EINVAL, "exceptions_cap above ESQ_EXCEPTIONS_CAP_MAX");
+    if (exceptions_cap && !out_exceptions)
+        return fail(ESQ_EINVAL, "out_exceptions is null but exceptions_cap > 0");
+    if (hi > (*c)->max_hi)
+        return fail(ESQ_ERANGE, "hi above the max_hi given to esq_init");
+    const uint64_t n0 = std::max<uint64_t>(lo, 3) | 1;
+    const uint64_t n_odd = hi > n0 ? (hi - n0 + 1) / 2 : 0;
+    reqs->assign(1, Req());
+    Req& r = (*reqs)[0];
+    r.I0 = (n0 - 1) / 2;
+    r.I1 = r.I0 + n_odd;
+    r.out_mink = d_out_mink;
+    r.out_bits = nullptr;
+    return ESQ_OK;
+}
+
 }  // namespace
 
 // A prepared batch: planned once, scratch and descriptors resident, launched
@@ -809,6 +851,14 @@ int esq_init(int device, uint64_t max_hi)
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
+    // the no-alloc entry point's scratch: its address on this device, taken
+    // once with the device current
+    if (device >= 0 && device < kMaxDevices && !g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess || !p)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[device] = (char*)p;
+    }
     bool fresh = false;
     if (!g_ctx) {
         g_ctx = new Ctx();
@@ -947,30 +997,49 @@ int esq_verify_range(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t* d_out_min
     t_err.clear();
     Ctx* c;
     Params par;
-    int rc = snapshot(&c, &par);
+    std::vector<Req> reqs;
+    int rc = verify_range_args(lo, hi, kmax, d_out_mink, out_summary, out_exceptions,
+                               exceptions_cap, &c, &par, &reqs);
     if (rc)
         return rc;
-    if (!out_summary)
-        return fail(ESQ_EINVAL, "out_summary is null");
-    if (kmax > 63)
-        return fail(ESQ_EINVAL, "kmax > 63");
-    if (lo > hi)
-        return fail(ESQ_EINVAL, "lo > hi");
-    if (exceptions_cap > ESQ_EXCEPTIONS_CAP_MAX)
-        return fail(ESQ_EINVAL, "exceptions_cap above ESQ_EXCEPTIONS_CAP_MAX");
-    if (exceptions_cap && !out_exceptions)
-        return fail(ESQ_EINVAL, "out_exceptions is null but exceptions_cap > 0");
-    if (hi > c->max_hi)
-        return fail(ESQ_ERANGE, "hi above the max_hi given to esq_init");
-    const uint64_t n0 = std::max<uint64_t>(lo, 3) | 1;
-    const uint64_t n_odd = hi > n0 ? (hi - n0 + 1) / 2 : 0;
-    std::vector<Req> reqs(1);
-    reqs[0].I0 = (n0 - 1) / 2;
-    reqs[0].I1 = reqs[0].I0 + n_odd;
-    reqs[0].out_mink = d_out_mink;
-    reqs[0].out_bits = nullptr;
     return enqueue(c, par, d_out_mink ? 1 : 0, kmax, reqs, out_summary, out_records,
                    exceptions_cap ? out_exceptions : nullptr, exceptions_cap, (hipStream_t)stream);
+}
+
+int esq_verify_range_noalloc(uint64_t lo, uint64_t hi, uint32_t kmax, uint8_t* d_out_mink,
+                             esq_summary* out_summary, esq_record* out_records,
+                             uint64_t* out_exceptions, uint64_t exceptions_cap, void* stream)
+{
+    t_err.clear();
+    Ctx* c;
+    Params par;
+    std::vector<Req> reqs;
+    int rc = verify_range_args(lo, hi, kmax, d_out_mink, out_summary, out_exceptions,
+                               exceptions_cap, &c, &par, &reqs);
+    if (rc)
+        return rc;
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (c->device >= 0 && c->device < kMaxDevices)
+            base = g_scratch_ptr[c->device];
+    }
+    if (!base)
+        return fail(ESQ_ENOINIT, "no static scratch on this device (device index above 63)");
+    Planned P;
+    const bool exc_list = exceptions_cap != 0;
+    if ((rc = plan(c, par, d_out_mink ? 1 : 0, kmax, reqs, exc_list, &P, true)))
+        return rc;
+    if (P.bytes > ESQ_NOALLOC_SCRATCH_MAX)
+        return fail(ESQ_ERANGE, "interval needs " + std::to_string(P.bytes) +
+                                    " bytes of scratch, above the static " +
+                                    std::to_string(ESQ_NOALLOC_SCRATCH_MAX) +
+                                    " (ESQ_NOALLOC_SCRATCH_MAX)");
+    bind(&P, base);
+    // the single interval's descriptor travels as a kernel argument: no
+    // upload, no staging buffer; no profiling events either
+    return launch_seq(P, true, false, out_summary, out_records,
+                      exc_list ? out_exceptions : nullptr, exceptions_cap, (hipStream_t)stream);
 }
 
 int esq_verify_batch(uint32_t count, const uint64_t* lo, const uint64_t* hi, uint32_t kmax,

@@ -19,13 +19,15 @@ LIB_PATH = os.path.join(_HERE, "libesq.so")
 ESQ_RECORDS_CAP = 64
 ESQ_EXCEPTIONS_CAP_MAX = 16384
 ESQ_MAX_HI = 1 << 56
+ESQ_NOALLOC_SCRATCH_MAX = 64 << 20
 STATUS_TAIL_OVERFLOW = 1
 STATUS_BUCKET_OVERFLOW = 2
 STATUS_EXCEPTIONS_INCOMPLETE = 4
 RECORD_KMAX_LIMIT = 1
 
 # every function declared in include/esq.h
-EXPORTS = ("esq_init", "esq_sieve_segment", "esq_verify_range", "esq_verify_batch",
+EXPORTS = ("esq_init", "esq_sieve_segment", "esq_verify_range", "esq_verify_range_noalloc",
+           "esq_verify_batch",
            "esq_batch_create", "esq_batch_launch", "esq_batch_destroy",
            "esq_scratch_bytes",
            "esq_set_param", "esq_get_param", "esq_profile_take", "esq_phase_take",
@@ -94,6 +96,8 @@ def lib():
         L.esq_sieve_segment.restype = ctypes.c_int
         L.esq_verify_range.argtypes = [u64, u64, u32, vp, vp, vp, vp, u64, vp]
         L.esq_verify_range.restype = ctypes.c_int
+        L.esq_verify_range_noalloc.argtypes = [u64, u64, u32, vp, vp, vp, vp, u64, vp]
+        L.esq_verify_range_noalloc.restype = ctypes.c_int
         L.esq_verify_batch.argtypes = [u32, vp, vp, u32, vp, vp, vp, vp]
         L.esq_verify_batch.restype = ctypes.c_int
         L.esq_batch_create.argtypes = [u32, vp, vp, u32, vp, vp, vp, ctypes.POINTER(vp)]
@@ -227,7 +231,7 @@ def sieve_segment(lo: int, hi: int, out=None, stream=None):
 class Pending:
     """Device buffers of one enqueued esq_verify_range call."""
 
-    def __init__(self, lo, hi, kmax, per_n, exceptions_cap, stream):
+    def __init__(self, lo, hi, kmax, per_n, exceptions_cap, stream, noalloc=False):
         self.lo, self.hi, self.kmax = int(lo), int(hi), int(kmax)
         n0 = max(self.lo, 3) | 1
         self.n_odd = (self.hi - n0 + 1) // 2 if self.hi > n0 else 0
@@ -239,7 +243,8 @@ class Pending:
                            if self.exc_cap else None)
         self.per_n = _per_n_buffer(n0, self.n_odd, dev) if per_n else None
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().esq_verify_range(
+        call = lib().esq_verify_range_noalloc if noalloc else lib().esq_verify_range
+        _check(call(
             self.lo, self.hi, self.kmax, _ptr(self.per_n), _ptr(self.summary),
             _ptr(self.records), _ptr(self.exceptions), self.exc_cap,
             ctypes.c_void_p(self.stream.cuda_stream)))
@@ -281,16 +286,21 @@ class Pending:
         return out
 
 
-def verify_range_async(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None) -> Pending:
-    """Enqueue Algorithm 2 over the odd n in [lo, hi); returns a Pending."""
-    return Pending(lo, hi, kmax, per_n, exceptions_cap, stream)
+def verify_range_async(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None,
+                       noalloc=False) -> Pending:
+    """Enqueue Algorithm 2 over the odd n in [lo, hi); returns a Pending.
+    noalloc=True goes through esq_verify_range_noalloc (the library's static
+    scratch; calls on one device must not overlap)."""
+    return Pending(lo, hi, kmax, per_n, exceptions_cap, stream, noalloc)
 
 
-def verify_range(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None, check=True) -> dict:
+def verify_range(lo, hi, kmax=0, per_n=False, exceptions_cap=0, stream=None, check=True,
+                 noalloc=False) -> dict:
     """Algorithm 2 over every odd n >= 3 in [lo, hi) plus the aggregates
     (per-k counts, sum of k, maximum k, record-setters, exceptions).  With
     per_n=True the result holds "per_n", a uint8 CUDA tensor of least k."""
-    return verify_range_async(lo, hi, kmax, per_n, exceptions_cap, stream).result(check=check)
+    return verify_range_async(lo, hi, kmax, per_n, exceptions_cap, stream,
+                              noalloc).result(check=check)
 
 
 def _parse(summary_bytes, record_bytes):

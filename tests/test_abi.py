@@ -52,6 +52,7 @@ def test_calls_before_init_fail_cleanly():
     assert b"esq_init" in L.esq_last_error()
     rc = L.esq_sieve_segment(1, 100, None, None)
     assert rc == -5
+    assert L.esq_verify_range_noalloc(3, 100, 0, None, None, None, None, 0, None) == -5
     lo = (ctypes.c_uint64 * 1)(3)
     hi = (ctypes.c_uint64 * 1)(1001)
     out = ctypes.c_uint64(7)
