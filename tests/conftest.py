@@ -32,3 +32,14 @@ def read_golden(name):
                 continue
             rows.append(line.split())
     return rows
+
+
+def load_oracle_sample(name):
+    """A stored oracle sample (tests/golden/make_oracle_samples.py): (meta,
+    ns, k, parts), with the drawn n regenerated and checked."""
+    import importlib.util
+    path = os.path.join(ROOT, "tests", "golden", "make_oracle_samples.py")
+    spec = importlib.util.spec_from_file_location("make_oracle_samples", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load(name)

@@ -168,16 +168,18 @@ def make(name, threads):
 
 
 def load(name):
-    """(meta dict, ns uint64 array, k uint8 array) of a stored sample; the
-    drawn n are regenerated and checked against the stored SHA-256."""
+    """(meta dict, ns uint64 array, k uint8 array, parts) of a stored sample;
+    the drawn n are regenerated and checked against the stored SHA-256.
+    parts: per window, batch interval or request, (lo, hi, start, stop,
+    full) -- its n are ns[start:stop]; full = every odd n of [lo, hi)."""
     with open(os.path.join(OUT, name + ".json")) as f:
         meta = json.load(f)
     with lzma.open(os.path.join(OUT, name + ".k.xz"), "rb") as f:
         k = np.frombuffer(f.read(), dtype=np.uint8)
-    ns, _ = draw(SAMPLES[name])
+    ns, parts = draw(SAMPLES[name])
     assert sha_n(ns) == meta["sha256_n"], "the seeded generator no longer draws the stored n"
     assert k.size == ns.size
-    return meta, ns, k
+    return meta, ns, k, parts
 
 
 def main():

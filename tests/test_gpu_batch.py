@@ -7,6 +7,7 @@ import torch
 
 import oracle
 from paper_2411_01964_amd import esq, workloads
+from tests.conftest import load_oracle_sample
 
 pytestmark = pytest.mark.gpu
 DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
@@ -80,16 +81,42 @@ def test_batch_kmax_and_repeat():
         same(a[i], esq.verify_range(x, y, kmax=2))
 
 
-def test_batch_config4_sample_equals_alone():
-    """The first 32 intervals of the seeded 4096-interval workload (lengths
-    2^16..2^28, starts in [2^30, 2^50)), batched vs alone."""
+def test_batch_workload_equals_alone_and_oracle():
+    """The seeded batched workload in full: 4096 intervals (lengths
+    2^16..2^28 odd n, starts in [2^30, 2^50)) in one launch, as benchmarked,
+    equal each interval alone for all 4096; then the same batch in per-n
+    mode, in chunks of intervals, gives the same aggregates and the oracle's
+    least k at 64 stored seeded n of every interval."""
     for k, v in DEFAULTS.items():
         esq.set_param(k, v)
     lo, hi = workloads.batch_intervals(seed=4, count=4096)
-    lo, hi = lo[:32], hi[:32]
     batch = esq.verify_batch(lo, hi)
-    for i, (a, b) in enumerate(zip(lo, hi)):
-        same(batch[i], esq.verify_range(a, b))
+    pend = [esq.verify_range_async(a, b) for a, b in zip(lo, hi)]
+    for i, p in enumerate(pend):
+        same(batch[i], p.result())
+    del pend
+    meta, ns, k, parts = load_oracle_sample("cfg4_sample")
+    assert len(parts) == 4096
+    budget = 1 << 32                          # per-n bytes per chunk
+    i = 0
+    while i < 4096:
+        j, total = i, 0
+        while j < 4096 and (j == i or total + batch[j]["n_odd"] <= budget):
+            total += batch[j]["n_odd"]
+            j += 1
+        res = esq.verify_batch(lo[i:j], hi[i:j], per_n=[True] * (j - i))
+        for t in range(i, j):
+            a, b, start, stop, _ = parts[t]
+            assert (a, b) == (lo[t], hi[t])
+            r = res[t - i]
+            same(r, batch[t])
+            idx = torch.from_numpy(((ns[start:stop] - np.uint64(r["n0"])) // np.uint64(2))
+                                   .astype(np.int64)).cuda()
+            got = r["per_n"][idx].cpu().numpy()
+            assert np.array_equal(got, k[start:stop]), (t, a, b)
+        del res
+        torch.cuda.empty_cache()
+        i = j
 
 
 def test_prepared_batch_and_graph_replays():

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2411_01964_amd import esq, workloads
-from tests.conftest import read_golden
+from tests.conftest import load_oracle_sample, read_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -58,9 +58,14 @@ def test_table4_and_table3_below_2pow30_on_gpu():
     assert g["kmax_seen"] == 9 and g["n_exceptions"] == 0
 
 
-@pytest.mark.parametrize("name,sample,seed", [("odd_2pow31_at_2pow40", 4096, 22),
-                                              ("odd_2pow33_below_2pow50", 1024, 33)])
-def test_full_interval(name, sample, seed):
+@pytest.mark.parametrize("name,samples", [
+    ("odd_2pow31_at_2pow40", ("cfg2_random", "cfg2_windows")),
+    ("odd_2pow33_below_2pow50", ("cfg3_random", "cfg3_windows"))])
+def test_full_interval(name, samples):
+    """The benchmarked call over the whole interval, then the same interval in
+    per-n mode: equal aggregates, and the per-n bytes equal the oracle's least
+    k at 2^20 stored seeded random n and at every n of the stored seeded
+    windows (64 of 2^16 n at 2^40, 16 of 2^12 n near 2^50)."""
     lo, hi = workloads.CONFIGS[name]
     g = esq.verify_range(lo, hi)                       # the benchmarked call
     N = g["n_odd"]
@@ -71,16 +76,19 @@ def test_full_interval(name, sample, seed):
     assert g["kmax_seen"] <= 13                        # Theorem 1
     check_density(g["hist"], N)
     check_records_with_oracle(g)
-    # the per-n mode over the same interval: same counts, sampled n vs oracle
+    # the per-n mode over the same interval: same counts, stored oracle samples
     p = esq.verify_range(lo, hi, per_n=True)
     assert p["hist"] == g["hist"] and p["records"] == g["records"]
     per_n = p["per_n"]
     counts = torch.bincount(per_n, minlength=65).cpu().tolist()
     assert counts[:65] == g["hist"]
-    ns = workloads.random_odd(seed=seed, count=sample, lo=lo, hi=hi)
-    idx = torch.from_numpy(((ns - np.uint64(g["n0"])) // np.uint64(2)).astype(np.int64)).cuda()
-    got = per_n[idx].cpu().numpy()
-    assert np.array_equal(got, oracle.mink_many(ns))
+    for sname in samples:
+        meta, ns, k, parts = load_oracle_sample(sname)
+        assert ns.min() >= lo and ns.max() < hi
+        idx = torch.from_numpy(((ns - np.uint64(g["n0"])) // np.uint64(2)).astype(np.int64)).cuda()
+        got = per_n[idx].cpu().numpy()
+        bad = np.nonzero(got != k)[0]
+        assert bad.size == 0, (sname, int(bad.size), [(int(ns[i]), int(got[i]), int(k[i])) for i in bad[:5]])
     # record-setters are where the running maximum of per_n increases
     for n, k in g["records"]:
         assert int(per_n[(n - g["n0"]) // 2]) == k
@@ -88,15 +96,20 @@ def test_full_interval(name, sample, seed):
     torch.cuda.empty_cache()
 
 
-def test_full_interval_windows_vs_oracle():
-    """Seeded windows inside the benchmarked intervals, element by element."""
-    for name, width, seed in (("odd_2pow31_at_2pow40", 1 << 13, 2), ("odd_2pow33_below_2pow50", 1 << 10, 3)):
-        lo, hi = workloads.CONFIGS[name]
-        for a, b in workloads.random_windows(seed, 2, width, lo, hi):
-            g = esq.verify_range(a, b, per_n=True)
-            o = oracle.verify_range(a, b, per_n=True)
-            assert g["hist"] == o["hist"] and g["records"] == o["records"]
-            assert np.array_equal(g["per_n"].cpu().numpy(), o["per_n"])
+@pytest.mark.parametrize("sname", ["cfg2_windows", "cfg3_windows"])
+def test_full_interval_windows_vs_oracle(sname):
+    """The stored seeded windows inside the benchmarked intervals, each as a
+    call of its own: per-n bytes element by element and every aggregate
+    (histogram, sum, maximum, records, exceptions) equal the oracle's."""
+    meta, ns, k, parts = load_oracle_sample(sname)
+    full = {(f["lo"], f["hi"]): f for f in meta["full"]}
+    assert len(full) == len(parts) == meta["count"]
+    for a, b, start, stop, _ in parts:
+        g = esq.verify_range(a, b, per_n=True)
+        f = full[(a, b)]
+        assert g["hist"] == f["hist"] and g["ksum"] == f["ksum"] and g["kmax_seen"] == f["kmax_seen"]
+        assert g["records"] == [tuple(x) for x in f["records"]] and g["n_exceptions"] == f["n_exceptions"]
+        assert np.array_equal(g["per_n"].cpu().numpy(), k[start:stop]), (a, b)
 
 
 def mobius_np(n):
