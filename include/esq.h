@@ -243,6 +243,11 @@ void esq_batch_destroy(esq_batch *batch);
  *                per resident workgroup
  *   "runs_per_wg" single interval: runs of consecutive segments per resident
  *                workgroup (1..64)
+ *   "stagger"    segment kernel: start delay of each later-launched quarter
+ *                of the workgroups, in units of 64 clocks (0..4096; 0 = none;
+ *                default 72, about a quarter of a segment at seg_log2 18)
+ *   "priority"   segment kernel: 1 = raise the wave priority of workgroups
+ *                with more of their run left (default), 0 = off
  * Applies to calls made after it.  Returns ESQ_EINVAL for an unknown name
  * or a value out of range.
  */
@@ -272,15 +277,17 @@ int esq_phase_take(uint64_t *ticks);
 
 /*
  * Measured ceilings of the current device, for the rooflines of the segment
- * kernel (Section 3's sieve is LDS work, its search VALU work): microbenchmarks
- * of conflict-free LDS operations and of int32 VALU issue, eight 256-thread
- * workgroups per CU, best of three timed launches each.  out (host, 6 doubles)
- * receives: [0] ds_write_b64 bytes/s, [1] ds_read_b64 bytes/s, [2] ds_or_b32
- * bytes/s, and int32 VALU lane-operations/s of [3] v_add_u32/v_xor_b32,
- * [4] v_alignbit_b32, [5] v_bcnt_u32_b32.  Synchronous; allocates and frees
- * a small device buffer.  Returns ESQ_EINVAL for a null pointer, ESQ_ENOMEM or
- * ESQ_EHIP on a HIP failure.
+ * kernel (Section 3's sieve is LDS work, its search VALU work, the pattern
+ * init L2 reads): microbenchmarks of conflict-free LDS operations, of int32
+ * VALU issue and of L2 reads, eight 256-thread workgroups per CU, best of
+ * three timed launches each.  out (host, ESQ_CEILINGS doubles) receives:
+ * [0] ds_write_b64 bytes/s, [1] ds_read_b64 bytes/s, [2] ds_or_b32 bytes/s,
+ * int32 VALU lane-operations/s of [3] v_add_u32/v_xor_b32, [4] v_alignbit_b32,
+ * [5] v_bcnt_u32_b32, and [6] L2 read bytes/s of 16-byte loads over a 1 MiB
+ * buffer.  Synchronous; allocates and frees small device buffers.  Returns
+ * ESQ_EINVAL for a null pointer, ESQ_ENOMEM or ESQ_EHIP on a HIP failure.
  */
+#define ESQ_CEILINGS 7
 int esq_measure_ceilings(double *out);
 
 /* Message for the last non-zero return on the calling thread ("" if none). */

@@ -58,6 +58,8 @@ struct Params {
     int64_t bucket_cap = 0;     // hit slots per segment; 0 = from the expected count
     int64_t items_per_wg = 4;   // batch: work items per resident workgroup
     int64_t runs_per_wg = 1;    // one interval: runs per resident workgroup
+    int64_t stagger = 72;       // segment kernel: start delay per workgroup slot (x 64 clocks)
+    int64_t priority = 1;       // segment kernel: wave priority from the share of the run left
 };
 
 struct MedTable {
@@ -651,6 +653,8 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.med_end = med_end;
     L.n_tasks = n_tasks;
     L.tasks_in_lds = tasks_in_lds ? 1u : 0u;
+    L.stagger = (uint32_t)par.stagger;
+    L.priority = (uint32_t)par.priority;
     L.phase = par.phase_clock ? c->d_phase : nullptr;
     L.stage = stage ? 1u : 0u;
     L.k_lds = mode == 2 ? 0 : klds;
@@ -1266,6 +1270,14 @@ int esq_set_param(const char* name, int64_t value)
         if (value < 1 || value > 64)
             return fail(ESQ_EINVAL, "runs_per_wg out of range");
         g_par.runs_per_wg = value;
+    } else if (n == "stagger") {
+        if (value < 0 || value > 4096)
+            return fail(ESQ_EINVAL, "stagger out of range");
+        g_par.stagger = value;
+    } else if (n == "priority") {
+        if (value < 0 || value > 1)
+            return fail(ESQ_EINVAL, "priority must be 0 or 1");
+        g_par.priority = value;
     } else {
         return fail(ESQ_EINVAL, "unknown parameter " + n);
     }
@@ -1296,6 +1308,8 @@ int64_t esq_get_param(const char* name)
     if (n == "bucket_cap") return g_par.bucket_cap;
     if (n == "items_per_wg") return g_par.items_per_wg;
     if (n == "runs_per_wg") return g_par.runs_per_wg;
+    if (n == "stagger") return g_par.stagger;
+    if (n == "priority") return g_par.priority;
     return -1;
 }
 

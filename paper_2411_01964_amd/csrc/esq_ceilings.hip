@@ -1,7 +1,9 @@
 // Measured ceilings of the device for the rooflines of the segment kernel:
-// LDS bandwidth of conflict-free ds_write_b64, ds_read_b64 and ds_or_b32, and
-// the int32 VALU issue rate of full-rate operations and of the search's
-// funnel shift and popcount.  Each microbenchmark runs eight 256-thread
+// LDS bandwidth of conflict-free ds_write_b64, ds_read_b64 and ds_or_b32, the
+// int32 VALU issue rate of full-rate operations and of the search's funnel
+// shift and popcount, and the L2 read bandwidth of 16-byte loads over an
+// L2-resident buffer (what the segment init streams from the pattern
+// tables).  Each microbenchmark runs eight 256-thread
 // workgroups per CU (8 waves per SIMD) with the operations in inline assembly,
 // so that none is removed or merged by the compiler.
 #include <hip/hip_runtime.h>
@@ -17,7 +19,8 @@ namespace ceil {
 
 constexpr uint32_t kCeilBlock = 256;
 constexpr uint32_t kCeilLdsBytes = 16384;  // 8 operations x 256 lanes x 8 bytes
-constexpr int kCeilings = 6;
+constexpr int kCeilings = 7;
+constexpr uint32_t kCeilL2Bytes = 1u << 20;  // L2-resident buffer (each XCD's L2 holds 4 MiB)
 
 // OP 0: ds_write_b64, 1: ds_read_b64, 2: ds_or_b32.  Lane l touches bytes
 // 8l .. 8l+7 (4l .. 4l+3 for ds_or_b32) of each 2 KB (1 KB) block, so every
@@ -168,6 +171,27 @@ __global__ __launch_bounds__(kCeilBlock) void k_ceil_valu(uint64_t* sink, uint32
     sink[(size_t)blockIdx.x * kCeilBlock + tid] = (uint64_t)(x0 ^ x1 ^ x2 ^ x3 ^ x4 ^ x5 ^ x6 ^ x7);
 }
 
+typedef uint32_t u32x4c __attribute__((ext_vector_type(4)));
+
+// 16-byte loads over a 1 MiB buffer: each workgroup reads consecutive 4 KB
+// blocks (256 lanes x 16 bytes) from its own start, eight blocks per
+// iteration, as the segment init reads consecutive table words.  Every index
+// is masked into the buffer.
+__global__ __launch_bounds__(kCeilBlock) void k_ceil_l2(const u32x4c* buf, uint64_t* sink, uint32_t iters)
+{
+    constexpr uint32_t mask = kCeilL2Bytes / 16 - 1;
+    const uint32_t tid = threadIdx.x;
+    uint32_t base = (blockIdx.x * 8u * kCeilBlock) & mask;
+    u32x4c acc = {0u, 0u, 0u, 0u};
+    for (uint32_t i = 0; i < iters; i++) {
+#pragma unroll
+        for (uint32_t r = 0; r < 8; r++)
+            acc ^= buf[(base + r * kCeilBlock + tid) & mask];
+        base = (base + 8u * kCeilBlock) & mask;
+    }
+    sink[(size_t)blockIdx.x * kCeilBlock + tid] = (uint64_t)(acc.x ^ acc.y ^ acc.z ^ acc.w);
+}
+
 }  // namespace ceil
 }  // namespace esq
 
@@ -184,17 +208,24 @@ extern "C" int esq_measure_ceilings(double* out)
         return ESQ_EHIP;
     const uint32_t grid = (uint32_t)n_cu * 8u;
     uint64_t* sink = nullptr;
+    u32x4c* l2buf = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ESQ_OK;
     if (hipMalloc(&sink, (size_t)grid * kCeilBlock * sizeof(uint64_t)) != hipSuccess)
         return ESQ_ENOMEM;
+    if (hipMalloc(&l2buf, kCeilL2Bytes) != hipSuccess) {
+        (void)hipFree(sink);
+        return ESQ_ENOMEM;
+    }
+    if (hipMemset(l2buf, 0x5a, kCeilL2Bytes) != hipSuccess)
+        rc = ESQ_EHIP;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rc = ESQ_EHIP;
     // bytes (or lane-operations) per thread per iteration
-    const double per_iter[kCeilings] = {64.0, 64.0, 32.0, 64.0, 64.0, 64.0};
-    const uint32_t iters[kCeilings] = {1024, 1024, 1024, 512, 256, 256};
+    const double per_iter[kCeilings] = {64.0, 64.0, 32.0, 64.0, 64.0, 64.0, 128.0};
+    const uint32_t iters[kCeilings] = {1024, 1024, 1024, 512, 256, 256, 128};
     for (int t = 0; t < kCeilings && rc == ESQ_OK; t++) {
         float best = 0.f;
         for (int rep = 0; rep < 4 && rc == ESQ_OK; rep++) {
@@ -212,8 +243,10 @@ extern "C" int esq_measure_ceilings(double* out)
                 hipLaunchKernelGGL(k_ceil_valu<0>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
             else if (t == 4)
                 hipLaunchKernelGGL(k_ceil_valu<1>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
-            else
+            else if (t == 5)
                 hipLaunchKernelGGL(k_ceil_valu<2>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
+            else
+                hipLaunchKernelGGL(k_ceil_l2, dim3(grid), dim3(kCeilBlock), 0, s, l2buf, sink, iters[t]);
             float ms = 0.f;
             if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -233,5 +266,6 @@ extern "C" int esq_measure_ceilings(double* out)
     if (s)
         (void)hipStreamDestroy(s);
     (void)hipFree(sink);
+    (void)hipFree(l2buf);
     return rc;
 }

@@ -89,6 +89,8 @@ struct Launch {
     const uint2* medq;            // per medium prime: (q, S mod q)
     const uint2* tasks;           // medium-prime lane-tasks
     uint32_t tasks_in_lds;        // 1: the task table is copied into LDS
+    uint32_t stagger;             // start delay per workgroup slot, in units of 64 clocks (0: none)
+    uint32_t priority;            // 1: wave priority from the share of the run left
     unsigned long long* phase;    // non-null: per-phase clock ticks of the segment loop (init, marking, search or store, segments)
     const uint64_t* wheel;        // kWheelPeriod + kWheelExtra words (9, 25, 49)
     const uint64_t* wheel2;       // kWheel2Period + kWheelExtra words (121, 169)

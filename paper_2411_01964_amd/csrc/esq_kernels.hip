@@ -322,11 +322,17 @@ __device__ __forceinline__ void store_depths(uint8_t* out, const uint32_t (&D)[1
 
 __device__ __forceinline__ void mark(uint32_t* bm32, uint32_t pos)
 {
-    // the word index through an opaque shift, so that the address becomes one
-    // shift-and-add instead of shift, mask and add
-    uint32_t wi;
-    asm("v_lshrrev_b32 %0, 5, %1" : "=v"(wi) : "v"(pos));
-    atomicOr(&bm32[wi], 1u << (pos & 31));
+    // the byte address of the word as (pos >> 3) & ~3: one shift (a half-rate
+    // operation on this chip, like the mask's) and one full-rate AND, where
+    // (pos >> 5) << 2 would take two shifts
+    // The bitmap starts at LDS address 0 (the kernel has no static LDS), so
+    // the byte offset is the LDS address itself.
+    (void)bm32;
+    uint32_t a;
+    asm("v_lshrrev_b32 %0, 3, %1" : "=v"(a) : "v"(pos));
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
+    lds_u32* w = (lds_u32*)(uintptr_t)(a & ~3u);
+    __hip_atomic_fetch_or(w, 1u << (pos & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Store bytes [b0, b1) of the 16 bytes v at the 16-byte aligned p (b0, b1
@@ -501,6 +507,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
         }
     };
 
+    // optional start delay by launch-order slot (the workgroups sharing a CU
+    // come from different quarters of the grid), so that their phases --
+    // L2-bound init, LDS-bound marking, VALU-bound search -- do not line up
+    if (L.stagger) {
+        const uint32_t slot = (uint32_t)(((uint64_t)blockIdx.x * 4u) / gridDim.x);
+        for (uint32_t i = 0; i < slot * L.stagger; i++)
+            __builtin_amdgcn_s_sleep(1);
+    }
+
     for (;;) {
         if (tid == 0) {
             uint32_t ok = 0, ivi = 0, b = 0, cnt = 0;
@@ -567,7 +582,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             // sharing a CU the first-launched would finish far ahead of the
             // last.  Raising the priority of a workgroup with more of its run
             // left keeps them level, and the CU busy until the end.
-            {
+            if (L.priority) {
                 const uint32_t q = min(((seg0 + nsegs - seg) * 4u) / nsegs, 3u);
                 if (q == 0)
                     __builtin_amdgcn_s_setprio(0);
@@ -668,13 +683,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             //    from the segment's hit slots (directly if the slots overflowed)
             // A prime with h = ceil(R / q) hits per region has c <= h tasks, so
             // c q <= R + q and f + v q < R + q: 32-bit positions suffice.
+            // v > 0 and c > 1 only when q < R < 2^21, and then c q <= R + q;
+            // with q clamped to 2^23 (> R: a prime with q > R has c = 1, v = 0
+            // and at most one hit, after which pos + step > R) both products
+            // fit 24-bit operands: full-rate 24-bit multiplies
             auto mark_tasks = [&](const uint2* tk_table) {
                 for (uint32_t e = tid; e < L.n_tasks; e += T) {
                     const uint2 tk = tk_table[e];
                     const uint32_t idx = tk.x & 0xffffu, v = tk.x >> 16, c = tk.y;
-                    const uint32_t q = s_medq[idx].x;
-                    const uint32_t step = c * q;
-                    for (uint32_t pos = s_f[idx] + v * q; pos < R; pos += step)
+                    const uint32_t q = min(s_medq[idx].x, 1u << 23);
+                    const uint32_t step = __umul24(c, q);
+                    for (uint32_t pos = s_f[idx] + __umul24(v, q); pos < R; pos += step)
                         mark(bm32, pos);
                 }
             };
@@ -822,10 +841,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     }
                     ulo &= wlo;
                     uhi &= whi;
-                    if (k <= kRegLevels)
+                    // levels below 4 are counted here; from level 4 on, where
+                    // the empty-wave test runs first, after that test (a wave
+                    // that stops there has nothing to count)
+                    if (k < 4)
                         cnt[k] = bcnt_acc(uhi, bcnt_acc(ulo, cnt[k]));
-                    else if (ulo | uhi)
-                        atomicAdd(&s_cnt[k], (uint32_t)(__popc(ulo) + __popc(uhi)));
                     if (MODE == 1) {
 #pragma unroll
                         for (int b = 0; b < 4; b++) {
@@ -843,6 +863,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         if (bal == 0) {
                             alive = false;
                             break;
+                        }
+                        if (k >= 4) {
+                            if (k <= kRegLevels)
+                                cnt[k] = bcnt_acc(uhi, bcnt_acc(ulo, cnt[k]));
+                            else if (ulo | uhi)
+                                atomicAdd(&s_cnt[k], (uint32_t)(__popc(ulo) + __popc(uhi)));
                         }
                         if (track) {
                             const uint32_t l = rfl((uint32_t)(__ffsll((unsigned long long)bal) - 1));

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 MAX_HI = (1 << 50) + (1 << 33)
 DEFAULTS = dict(seg_log2=18, sieve_seg_log2=19, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
-                medium_max=4095, bucket_cap=0, items_per_wg=4)
+                medium_max=4095, bucket_cap=0, items_per_wg=4, stagger=72, priority=1, runs_per_wg=1)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -94,6 +94,7 @@ def test_config1_full_exact():
     dict(entry_hits=1), dict(entry_hits=4096), dict(seg_log2=11, kh=9, block=128),
     dict(medium_max=11), dict(medium_max=11000), dict(medium_max=101, bucket_cap=1),
     dict(block=256, medium_max=8191), dict(seg_log2=16, block=128),
+    dict(stagger=0, priority=0), dict(stagger=4096, priority=0), dict(stagger=0, runs_per_wg=7),
 ])
 def test_knob_invariance(kw):
     knobs(**kw)
@@ -278,6 +279,7 @@ def test_phase_clock_and_ceilings():
         assert 1e12 < c[k] < 1e15, (k, c[k])
     for k in ("valu_int32_ops_per_s", "valu_alignbit_ops_per_s", "valu_bcnt_ops_per_s"):
         assert 1e12 < c[k] < 1e15, (k, c[k])
+    assert 1e12 < c["l2_read_Bps"] < 1e15
 
 
 def test_near_the_largest_supported_n():
