@@ -367,7 +367,7 @@ def bench_batched(steps, ceil):
 
     lo, hi = workloads.batch_intervals(seed=4, count=4096)
     n_total = sum(n_odd_of(a, b) for a, b in zip(lo, hi))
-    defaults = {k: esq.get_param(k) for k in ("seg_log2", "block", "medium_max", "items_per_wg")}
+    defaults = {k: esq.get_param(k) for k in ("seg_log2", "block", "medium_max", "items_per_wg", "stagger")}
     knobs = load_tuned("batch_4096_intervals")
     tune.apply(knobs)
     pb = esq.PreparedBatch(lo, hi)
