@@ -243,9 +243,10 @@ void esq_batch_destroy(esq_batch *batch);
  *                per resident workgroup
  *   "runs_per_wg" single interval: runs of consecutive segments per resident
  *                workgroup (1..64)
- *   "stagger"    segment kernel: start delay of each later-launched quarter
- *                of the workgroups, in units of 64 clocks (0..4096; 0 = none;
- *                default 72, about a quarter of a segment at seg_log2 18)
+ *   "stagger"    segment kernel, summary mode: start delay of each
+ *                later-launched quarter of the workgroups, in units of 64
+ *                clocks (0..4096; 0 = none; default 72, about a quarter of a
+ *                segment at seg_log2 18)
  *   "priority"   segment kernel: 1 = raise the wave priority of workgroups
  *                with more of their run left (default), 0 = off
  * Applies to calls made after it.  Returns ESQ_EINVAL for an unknown name

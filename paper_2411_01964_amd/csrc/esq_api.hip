@@ -653,7 +653,9 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.med_end = med_end;
     L.n_tasks = n_tasks;
     L.tasks_in_lds = tasks_in_lds ? 1u : 0u;
-    L.stagger = (uint32_t)par.stagger;
+    // the stagger pays in summary mode only (measured: the per-n and sieve
+    // forms, bound by their HBM stores, are no faster with it)
+    L.stagger = mode == 0 ? (uint32_t)par.stagger : 0u;
     L.priority = (uint32_t)par.priority;
     L.phase = par.phase_clock ? c->d_phase : nullptr;
     L.stage = stage ? 1u : 0u;

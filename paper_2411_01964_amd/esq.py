@@ -55,6 +55,7 @@ class Record(ctypes.Structure):
 
 
 SUMMARY_BYTES = ctypes.sizeof(Summary)
+PER_N_SLAB = 544 << 20   # per-n output slab of a batch: any interval of up to 2^29 odd n fits
 RECORD_BYTES = ctypes.sizeof(Record)
 
 
@@ -366,18 +367,30 @@ class PendingBatch:
         self.per_n = None
         ptrs = None
         if per_n is not None and any(per_n):
-            self.per_n = []
+            # per-n outputs packed into slabs of one fixed size (a size the
+            # caching allocator hands out again and again), a larger output in
+            # an allocation of its own; each interval's bytes start at an
+            # address congruent to its first odd index mod 16 (as
+            # _per_n_buffer places a single one)
+            lo_l, hi_l = self.lo.tolist(), self.hi.tolist()
+            self.per_n = [None] * self.count
             ptrs = (ctypes.c_void_p * self.count)()
+            buf, base, off, cap = None, 0, 0, 0
             for i in range(self.count):
-                if per_n[i]:
-                    n0 = max(int(self.lo[i]), 3) | 1
-                    n_odd = (int(self.hi[i]) - n0 + 1) // 2 if int(self.hi[i]) > n0 else 0
-                    t = _per_n_buffer(n0, n_odd, dev)
-                    self.per_n.append(t[:n_odd])
-                    ptrs[i] = t.data_ptr()
-                else:
-                    self.per_n.append(None)
-                    ptrs[i] = None
+                if not per_n[i]:
+                    continue
+                n0 = max(lo_l[i], 3) | 1
+                n = (hi_l[i] - n0 + 1) // 2 if hi_l[i] > n0 else 0
+                need = max(n, 1) + 15
+                if buf is None or off + need > cap:
+                    cap = max(PER_N_SLAB, need)
+                    buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+                    base, off = buf.data_ptr(), 0
+                off += (((n0 - 1) // 2) - (base + off)) % 16
+                self.per_n[i] = buf[off:off + n]
+                ptrs[i] = base + off
+                off += max(n, 1)
+            del buf
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().esq_verify_batch(
             self.count, ctypes.c_void_p(self.lo.ctypes.data), ctypes.c_void_p(self.hi.ctypes.data),
@@ -397,6 +410,46 @@ class PendingBatch:
                 r["per_n"] = self.per_n[i]
             if check and r["status"]:
                 raise EsqError(-100, "device status 0x%x for interval %d" % (r["status"], i))
+        return out
+
+    def raw(self, check: bool = True) -> "BatchResults":
+        """The batch's results as arrays, parsed per interval on demand."""
+        self.event.synchronize()
+        return BatchResults(self.summaries, self.records, self.count, self.per_n, check)
+
+
+class BatchResults:
+    """Summaries and records of a batch copied to the host in two transfers;
+    interval i becomes the dict of verify_range only when asked for."""
+
+    def __init__(self, summaries, records, count, per_n, check):
+        self.count = count
+        self.sm = summaries[:count * SUMMARY_BYTES].cpu().numpy().view(SUMMARY_DTYPE)
+        self.rc = records[:count * ESQ_RECORDS_CAP * RECORD_BYTES].cpu().numpy().view(
+            RECORD_DTYPE).reshape(count, ESQ_RECORDS_CAP)
+        self.per_n = per_n
+        if check and count and self.sm["status"].any():
+            i = int(self.sm["status"].nonzero()[0][0])
+            raise EsqError(-100, "device status 0x%x for interval %d" % (int(self.sm["status"][i]), i))
+
+    def release_per_n(self, i):
+        """Drop the batch's reference to interval i's per-n bytes."""
+        if self.per_n is not None:
+            self.per_n[i] = None
+
+    def parse(self, i) -> dict:
+        s, rc = self.sm[i], self.rc[i]
+        nrec = min(int(s["n_records"]), ESQ_RECORDS_CAP)
+        out = {
+            "n0": int(s["n0"]), "n_odd": int(s["n_odd"]), "hist": s["hist"].tolist(),
+            "ksum": int(s["ksum"]), "kmax_seen": int(s["kmax_seen"]),
+            "n_records": int(s["n_records"]),
+            "records": list(zip(rc["n"][:nrec].tolist(), rc["k"][:nrec].tolist())),
+            "record_flags": rc["flags"][:nrec].tolist(),
+            "n_exceptions": int(s["n_exceptions"]), "status": int(s["status"]),
+        }
+        if self.per_n is not None and self.per_n[i] is not None:
+            out["per_n"] = self.per_n[i]
         return out
 
 

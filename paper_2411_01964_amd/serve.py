@@ -1,16 +1,21 @@
 """Serving: continuous batching of interval-verification requests.
 
 Requests (an interval [lo, hi) and whether the per-n least k is wanted)
-arrive at any time.  A scheduler thread admits waiting requests into a batch
-whenever a stream slot is free and the batch's HBM footprint fits the budget,
-and launches the batch with one esq_verify_batch call (one persistent kernel
-over a device work queue).  Batches on different streams overlap on the
-device, so requests that arrive while others run are admitted as soon as a
-slot and memory free up.  The prime table and the wheel pattern stay resident
-in the library's context; a batch's scratch is stream-ordered.
+arrive at any time.  A scheduler thread keeps two queues, per-n requests and
+summary requests, and whenever a stream slot is free it admits a batch from
+the queue whose oldest request has waited longest: one esq_verify_batch call
+(one persistent kernel over a device work queue).  Per-n and summary requests
+go in separate batches, so summary requests run in the segment kernel's
+summary form (twice the resident workgroups of the per-n form, no HBM
+writes).  A batch is admitted while its HBM footprint fits the budget: the
+scratch the library plans for exactly that batch (esq_scratch_bytes) plus its
+outputs.  Batches on different streams overlap on the device, so requests
+that arrive while others run are admitted as soon as a slot and memory free
+up.  The prime table and the pattern tables stay resident in the library.
 
 Results are exactly those of esq_verify_range on each interval alone (the
-tests check this); only latency and throughput depend on the mix.
+tests check this); only latency and throughput depend on the mix.  A
+request's result dict is built from the batch's arrays when it is first read.
 """
 from __future__ import annotations
 
@@ -23,17 +28,20 @@ import torch
 
 from . import esq
 
-# scratch bytes a batch needs per odd n besides the per-n output (hit slots,
-# counters), a conservative figure for sizing admission
-_SCRATCH_PER_N = 0.01
-_SCRATCH_PER_REQUEST = 64 << 10
+# per-request device bytes besides the per-n output, a planning estimate
+# (hit slots and counters per segment of 2^18 odd n, descriptors, outputs);
+# the batch's exact scratch comes from the library when it is admitted
+_SCRATCH_PER_SEGMENT = 400
+_SCRATCH_PER_REQUEST = 4 << 10
+_OUTPUT_PER_REQUEST = esq.SUMMARY_BYTES + esq.ESQ_RECORDS_CAP * esq.RECORD_BYTES
 
 
 def footprint(lo: int, hi: int, per_n: bool) -> int:
-    """HBM bytes a request holds while in flight."""
+    """Estimated HBM bytes a request holds while in flight."""
     n0 = max(int(lo), 3) | 1
     n = (int(hi) - n0 + 1) // 2 if int(hi) > n0 else 0
-    return int(n * _SCRATCH_PER_N) + _SCRATCH_PER_REQUEST + (n if per_n else 0)
+    return (((n >> 18) + 2) * _SCRATCH_PER_SEGMENT + _SCRATCH_PER_REQUEST +
+            _OUTPUT_PER_REQUEST + (n + 16 if per_n else 0))
 
 
 _gc_lock = threading.Lock()
@@ -59,19 +67,39 @@ def _gc_resume():
 
 
 class Request:
-    __slots__ = ("lo", "hi", "per_n", "t_arrival", "t_done", "result", "event", "bytes")
+    __slots__ = ("lo", "hi", "per_n", "t_arrival", "t_done", "bytes", "n_odd", "_result", "_src",
+                 "_srv")
 
-    def __init__(self, lo, hi, per_n, t_arrival):
+    def __init__(self, lo, hi, per_n, t_arrival, srv=None):
         self.lo, self.hi, self.per_n = int(lo), int(hi), bool(per_n)
+        n0 = max(self.lo, 3) | 1
+        self.n_odd = (self.hi - n0 + 1) // 2 if self.hi > n0 else 0
         self.t_arrival = t_arrival
         self.t_done = None
-        self.result = None
-        self.event = threading.Event()
         self.bytes = footprint(lo, hi, per_n)
+        self._result = None
+        self._src = None          # (BatchResults, index) until the result is read
+        self._srv = srv
+
+    @property
+    def result(self):
+        if self._src is not None:
+            batch, i = self._src
+            self._src = None
+            self._result = batch.parse(i)
+        return self._result
+
+    @result.setter
+    def result(self, value):
+        self._src = None
+        self._result = value
 
     def wait(self, timeout=None):
-        self.event.wait(timeout)
-        return self.result
+        """Block until the request is done (or the server failed); returns
+        the result dict, or None on a timeout or a server error."""
+        if self.t_done is None and self._srv is not None:
+            self._srv._wait_done(self, timeout)
+        return self.result if self.t_done is not None else None
 
 
 class Server:
@@ -91,13 +119,14 @@ class Server:
             _gc_pause()
             self._gc_paused = True
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
-        self.busy = [None] * n_streams          # (PendingBatch, [Request]) per stream
+        self.busy = [None] * n_streams          # (PendingBatch, [Request], bytes) per stream
         self.budget = int(hbm_budget)
         self.in_flight_bytes = 0
         self.max_batch = int(max_batch)
         self.kmax = int(kmax)
-        self.waiting = collections.deque()
+        self.queues = (collections.deque(), collections.deque())  # summary, per-n
         self.cv = threading.Condition()
+        self.done_cv = threading.Condition()
         self.running = True
         self.batches = 0
         self.error = None
@@ -112,11 +141,11 @@ class Server:
         self.thread.start()
 
     def submit(self, lo, hi, per_n=False) -> Request:
-        r = Request(lo, hi, per_n, time.perf_counter())
+        r = Request(lo, hi, per_n, time.perf_counter(), self)
         with self.cv:
             if self.error is not None:
                 raise self.error
-            self.waiting.append(r)
+            self.queues[1 if r.per_n else 0].append(r)
             self.cv.notify()
         return r
 
@@ -131,38 +160,72 @@ class Server:
         if self.error is not None:
             raise self.error
 
+    def _wait_done(self, r, timeout):
+        end = None if timeout is None else time.perf_counter() + timeout
+        with self.done_cv:
+            while r.t_done is None and self.error is None:
+                left = None if end is None else end - time.perf_counter()
+                if left is not None and left <= 0:
+                    return
+                self.done_cv.wait(left)
+
     # ------------------------------------------------------------ scheduler
     def _complete(self, i):
-        pend, reqs = self.busy[i]
-        res = pend.result(check=True)
+        pend, reqs, nbytes = self.busy[i]
+        res = pend.raw(check=True)
         now = time.perf_counter()
-        for r, x in zip(reqs, res):
-            r.result = x
+        for j, r in enumerate(reqs):
+            r._src = (res, j)
             r.t_done = now
-            self.in_flight_bytes -= r.bytes
             if self.on_done is not None:
                 self.on_done(r)
-            r.event.set()
+        self.in_flight_bytes -= nbytes
         self.busy[i] = None
+        with self.done_cv:
+            self.done_cv.notify_all()
 
     def _admit(self, i):
+        qs, qp = self.queues
+        if qs and (not qp or qs[0].t_arrival <= qp[0].t_arrival):
+            q = qs
+        elif qp:
+            q = qp
+        else:
+            return False
         batch, total = [], 0
-        while self.waiting and len(batch) < self.max_batch:
-            r = self.waiting[0]
+        while q and len(batch) < self.max_batch:
+            r = q[0]
             if batch and self.in_flight_bytes + total + r.bytes > self.budget:
                 break
             if not batch and self.in_flight_bytes + r.bytes > self.budget and any(self.busy):
                 break  # wait for memory to free up
-            batch.append(self.waiting.popleft())
+            batch.append(q.popleft())
             total += r.bytes
         if not batch:
             return False
-        self.in_flight_bytes += total
+        # the library's plan of exactly this batch: its scratch, plus the
+        # outputs; a batch that does not fit gives back its last requests
+        los, his = [r.lo for r in batch], [r.hi for r in batch]
+        while True:
+            exact = (esq.scratch_bytes(los, his, self.kmax) + len(batch) * _OUTPUT_PER_REQUEST +
+                     sum(r.n_odd + 16 for r in batch if r.per_n))
+            if len(batch) == 1 or self.in_flight_bytes + exact <= self.budget:
+                break
+            keep = max(1, len(batch) // 2)
+            for r in reversed(batch[keep:]):
+                q.appendleft(r)
+            del batch[keep:], los[keep:], his[keep:]
+        if self.in_flight_bytes + exact > self.budget and any(self.busy):
+            for r in reversed(batch):
+                q.appendleft(r)
+            return False
+        self.in_flight_bytes += exact
+        per_n = batch[0].per_n
         with torch.cuda.stream(self.streams[i]):
-            pend = esq.verify_batch_async([r.lo for r in batch], [r.hi for r in batch],
-                                          kmax=self.kmax, per_n=[r.per_n for r in batch],
+            pend = esq.verify_batch_async(los, his, kmax=self.kmax,
+                                          per_n=[True] * len(batch) if per_n else None,
                                           stream=self.streams[i])
-        self.busy[i] = (pend, batch)
+        self.busy[i] = (pend, batch, exact)
         self.batches += 1
         return True
 
@@ -175,32 +238,32 @@ class Server:
                         self._complete(i)
                         progressed = True
                 with self.cv:
-                    if not self.running and not self.waiting and not any(self.busy):
+                    if (not self.running and not self.queues[0] and not self.queues[1]
+                            and not any(self.busy)):
                         return
                     for i in range(len(self.streams)):
-                        if self.busy[i] is None and self.waiting:
+                        if self.busy[i] is None and (self.queues[0] or self.queues[1]):
                             progressed |= self._admit(i)
                     if not progressed:
                         if any(self.busy):
                             self.cv.wait(timeout=self.poll_s)
                         else:
                             self.cv.wait(timeout=0.01)
-        except Exception as e:  # surfaced to submitters and close()
+        except Exception as e:  # surfaced to submitters, waiters and close()
             self.error = e
             with self.cv:
-                while self.waiting:
-                    r = self.waiting.popleft()
-                    r.event.set()
-            for b in self.busy:
-                if b is not None:
-                    for r in b[1]:
-                        r.event.set()
+                for q in self.queues:
+                    q.clear()
+            with self.done_cv:
+                self.done_cv.notify_all()
 
 
 def _release_per_n(r):
     # the client has consumed the per-n array: give its memory back
-    if r.result is not None:
-        r.result.pop("per_n", None)
+    if r._src is not None:
+        r._src[0].release_per_n(r._src[1])
+    elif r._result is not None:
+        r._result.pop("per_n", None)
 
 
 def run_stream(requests, n_streams=4, hbm_budget=16 << 30, warmup_s=1.0, paced=True,
@@ -224,7 +287,7 @@ def run_stream(requests, n_streams=4, hbm_budget=16 << 30, warmup_s=1.0, paced=T
     wall = time.perf_counter() - t0
     srv.close()
     lat = sorted((r.t_done - r.t_arrival) for t, r in out if t >= warmup_s)
-    n_total = sum(r.result["n_odd"] for _, r in out if r.result is not None)
+    n_total = sum(r.n_odd for _, r in out if r.t_done is not None)
     stats = {
         "requests": len(out),
         "measured_requests": len(lat),
