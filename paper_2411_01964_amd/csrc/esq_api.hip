@@ -50,7 +50,7 @@ struct Params {
     int sieve_seg_log2 = 19;  // Algorithm 1 alone: fewer, longer segments (its stores do not overlap)
     int kh = 13;
     int block = 512;
-    int entry_hits = 16;
+    int entry_hits = 12;
     int64_t tail_cap = 1 << 20;
     int profile = 0;
     int phase_clock = 0;

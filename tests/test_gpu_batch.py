@@ -10,7 +10,7 @@ from paper_2411_01964_amd import esq, workloads
 from tests.conftest import load_oracle_sample
 
 pytestmark = pytest.mark.gpu
-DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
+DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=12, tail_cap=1 << 20,
                 medium_max=4095, bucket_cap=0, items_per_wg=4)
 
 

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module", autouse=True)
 def lib_ready():
     esq.init(0, (1 << 50) + (1 << 33))
-    for k, v in dict(seg_log2=18, kh=13, block=512, entry_hits=16, tail_cap=1 << 20).items():
+    for k, v in dict(seg_log2=18, kh=13, block=512, entry_hits=12, tail_cap=1 << 20).items():
         esq.set_param(k, v)
 
 

@@ -13,7 +13,7 @@ from tests.conftest import read_golden
 pytestmark = pytest.mark.gpu
 
 MAX_HI = (1 << 50) + (1 << 33)
-DEFAULTS = dict(seg_log2=18, sieve_seg_log2=19, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
+DEFAULTS = dict(seg_log2=18, sieve_seg_log2=19, kh=13, block=512, entry_hits=12, tail_cap=1 << 20,
                 medium_max=4095, bucket_cap=0, items_per_wg=4, stagger=72, priority=1, runs_per_wg=1)
 
 

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 KEYS = ("n0", "n_odd", "hist", "ksum", "kmax_seen", "records", "record_flags", "n_records",
         "n_exceptions", "exceptions", "status")
-DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=16, tail_cap=1 << 20,
+DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=12, tail_cap=1 << 20,
                 medium_max=4095, bucket_cap=0)
 
 
