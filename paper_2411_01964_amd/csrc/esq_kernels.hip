@@ -916,14 +916,21 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         pl[b][1] &= ~uhi;
                     }
                     // planes -> one byte per n: nibble t of plane b spread to
-                    // bit b of 4 bytes; plane 3 (least k >= 8) is almost never set
+                    // bit b of 4 bytes.  Plane 2 (least k in 4 .. 7) holds
+                    // 1.4e-4 of the n, so a wave of 4096 n has none more often
+                    // than not, and plane 3 (k >= 8) is almost never set: both
+                    // are spread only when some lane of the wave has a bit
                     uint32_t D[16];
 #pragma unroll
                     for (int t = 0; t < 16; t++) {
                         const int h = t >> 3, sh = 4 * (t & 7);
                         D[t] = (((pl[0][h] >> sh) & 15u) * 0x00204081u & 0x01010101u) |
-                               (((pl[1][h] >> sh) & 15u) * 0x00408102u & 0x02020202u) |
-                               (((pl[2][h] >> sh) & 15u) * 0x00810204u & 0x04040404u);
+                               (((pl[1][h] >> sh) & 15u) * 0x00408102u & 0x02020202u);
+                    }
+                    if (__ballot((pl[2][0] | pl[2][1]) != 0)) {
+#pragma unroll
+                        for (int t = 0; t < 16; t++)
+                            D[t] |= spread4((pl[2][t >> 3] >> (4 * (t & 7))) & 15u) << 2;
                     }
                     if (__ballot((pl[3][0] | pl[3][1]) != 0)) {
 #pragma unroll

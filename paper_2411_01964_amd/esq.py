@@ -353,7 +353,7 @@ def _parse_many(summaries, records, count):
 class PendingBatch:
     """Device buffers of one enqueued esq_verify_batch call."""
 
-    def __init__(self, los, his, kmax, per_n, stream):
+    def __init__(self, los, his, kmax, per_n, stream, host_bufs=None, alloc_stream=None):
         import numpy as np
         self.lo = np.ascontiguousarray(np.asarray(los, dtype=np.uint64))
         self.hi = np.ascontiguousarray(np.asarray(his, dtype=np.uint64))
@@ -384,7 +384,16 @@ class PendingBatch:
                 need = max(n, 1) + 15
                 if buf is None or off + need > cap:
                     cap = max(PER_N_SLAB, need)
-                    buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+                    if alloc_stream is None:
+                        buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+                    else:
+                        # from one stream's pool whichever stream runs the batch
+                        # (the caching allocator reuses a block only on the
+                        # stream it was allocated on); recorded on the batch's
+                        # stream so that it is not reused before the batch ends
+                        with torch.cuda.stream(alloc_stream):
+                            buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+                        buf.record_stream(stream if stream is not None else torch.cuda.current_stream())
                     base, off = buf.data_ptr(), 0
                 off += (((n0 - 1) // 2) - (base + off)) % 16
                 self.per_n[i] = buf[off:off + n]
@@ -396,6 +405,19 @@ class PendingBatch:
             self.count, ctypes.c_void_p(self.lo.ctypes.data), ctypes.c_void_p(self.hi.ctypes.data),
             int(kmax), ptrs, _ptr(self.summaries), _ptr(self.records),
             ctypes.c_void_p(self.stream.cuda_stream)))
+        # with host_bufs (pinned host tensors the caller reuses for one batch
+        # at a time), the summaries and records are copied there on the
+        # batch's own stream, so that they are on the host when its event
+        # completes
+        self.host_bufs = None
+        if host_bufs is not None:
+            hs, hr = host_bufs
+            if hs.numel() < self.summaries.numel() or hr.numel() < self.records.numel():
+                raise ValueError("host buffers too small for the batch")
+            self.host_bufs = (hs[:self.summaries.numel()], hr[:self.records.numel()])
+            with torch.cuda.stream(self.stream):
+                self.host_bufs[0].copy_(self.summaries, non_blocking=True)
+                self.host_bufs[1].copy_(self.records, non_blocking=True)
         self.event = torch.cuda.Event()
         self.event.record(self.stream)
 
@@ -413,8 +435,13 @@ class PendingBatch:
         return out
 
     def raw(self, check: bool = True) -> "BatchResults":
-        """The batch's results as arrays, parsed per interval on demand."""
+        """The batch's results as arrays, parsed per interval on demand (a
+        copy of the host buffers when the batch was given some, so that they
+        can take the next batch)."""
         self.event.synchronize()
+        if self.host_bufs is not None:
+            return BatchResults(self.host_bufs[0], self.host_bufs[1], self.count, self.per_n, check,
+                                copy=True)
         return BatchResults(self.summaries, self.records, self.count, self.per_n, check)
 
 
@@ -422,11 +449,15 @@ class BatchResults:
     """Summaries and records of a batch copied to the host in two transfers;
     interval i becomes the dict of verify_range only when asked for."""
 
-    def __init__(self, summaries, records, count, per_n, check):
+    def __init__(self, summaries, records, count, per_n, check, copy=False):
+        import numpy as np
         self.count = count
-        self.sm = summaries[:count * SUMMARY_BYTES].cpu().numpy().view(SUMMARY_DTYPE)
-        self.rc = records[:count * ESQ_RECORDS_CAP * RECORD_BYTES].cpu().numpy().view(
-            RECORD_DTYPE).reshape(count, ESQ_RECORDS_CAP)
+        sm = summaries[:count * SUMMARY_BYTES].cpu().numpy()
+        rc = records[:count * ESQ_RECORDS_CAP * RECORD_BYTES].cpu().numpy()
+        if copy:
+            sm, rc = np.array(sm), np.array(rc)
+        self.sm = sm.view(SUMMARY_DTYPE)
+        self.rc = rc.view(RECORD_DTYPE).reshape(count, ESQ_RECORDS_CAP)
         self.per_n = per_n
         if check and count and self.sm["status"].any():
             i = int(self.sm["status"].nonzero()[0][0])
@@ -453,9 +484,10 @@ class BatchResults:
         return out
 
 
-def verify_batch_async(los, his, kmax=0, per_n=None, stream=None) -> PendingBatch:
+def verify_batch_async(los, his, kmax=0, per_n=None, stream=None, host_bufs=None,
+                       alloc_stream=None) -> PendingBatch:
     """Enqueue many intervals in one launch (esq_verify_batch)."""
-    return PendingBatch(los, his, kmax, per_n, stream)
+    return PendingBatch(los, his, kmax, per_n, stream, host_bufs, alloc_stream)
 
 
 def verify_batch(los, his, kmax=0, per_n=None, stream=None, check=True) -> list:

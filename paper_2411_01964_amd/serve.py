@@ -105,7 +105,7 @@ class Request:
 class Server:
     """Continuous-batching server over the batched C-ABI call."""
 
-    def __init__(self, n_streams: int = 4, hbm_budget: int = 16 << 30, max_batch: int = 512,
+    def __init__(self, n_streams: int = 4, hbm_budget: int = 64 << 30, max_batch: int = 512,
                  kmax: int = 0, on_done=None, pause_gc: bool = True, poll_s: float = 0.0):
         # Python's cyclic garbage collector stops every thread while it scans
         # the heap: with tens of thousands of requests alive, a full pass takes
@@ -119,6 +119,13 @@ class Server:
             _gc_pause()
             self._gc_paused = True
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        # pinned host buffers per stream slot for a batch's summaries and
+        # records (copied on the batch's stream, read once it completes)
+        self.host_bufs = [(torch.empty(max_batch * esq.SUMMARY_BYTES, dtype=torch.uint8,
+                                       pin_memory=True),
+                           torch.empty(max_batch * esq.ESQ_RECORDS_CAP * esq.RECORD_BYTES,
+                                       dtype=torch.uint8, pin_memory=True))
+                          for _ in range(n_streams)]
         self.busy = [None] * n_streams          # (PendingBatch, [Request], bytes) per stream
         self.budget = int(hbm_budget)
         self.in_flight_bytes = 0
@@ -192,10 +199,16 @@ class Server:
             q = qp
         else:
             return False
+        # a batch takes at most its stream's share of the budget, so that
+        # several batches are queued on the device while the host completes
+        # and admits others (one batch holding the whole budget would leave
+        # the GPU idle for every turnaround)
+        share = self.budget // len(self.streams)
         batch, total = [], 0
         while q and len(batch) < self.max_batch:
             r = q[0]
-            if batch and self.in_flight_bytes + total + r.bytes > self.budget:
+            if batch and (self.in_flight_bytes + total + r.bytes > self.budget or
+                          total + r.bytes > share):
                 break
             if not batch and self.in_flight_bytes + r.bytes > self.budget and any(self.busy):
                 break  # wait for memory to free up
@@ -209,7 +222,7 @@ class Server:
         while True:
             exact = (esq.scratch_bytes(los, his, self.kmax) + len(batch) * _OUTPUT_PER_REQUEST +
                      sum(r.n_odd + 16 for r in batch if r.per_n))
-            if len(batch) == 1 or self.in_flight_bytes + exact <= self.budget:
+            if len(batch) == 1 or (self.in_flight_bytes + exact <= self.budget and exact <= share):
                 break
             keep = max(1, len(batch) // 2)
             for r in reversed(batch[keep:]):
@@ -224,7 +237,8 @@ class Server:
         with torch.cuda.stream(self.streams[i]):
             pend = esq.verify_batch_async(los, his, kmax=self.kmax,
                                           per_n=[True] * len(batch) if per_n else None,
-                                          stream=self.streams[i])
+                                          stream=self.streams[i], host_bufs=self.host_bufs[i],
+                                          alloc_stream=torch.cuda.default_stream())
         self.busy[i] = (pend, batch, exact)
         self.batches += 1
         return True
@@ -266,7 +280,7 @@ def _release_per_n(r):
         r._result.pop("per_n", None)
 
 
-def run_stream(requests, n_streams=4, hbm_budget=16 << 30, warmup_s=1.0, paced=True,
+def run_stream(requests, n_streams=4, hbm_budget=64 << 30, warmup_s=1.0, paced=True,
                keep_per_n=True, poll_s=0.0):
     """Drive a Server with (t_arrival_s, lo, hi, per_n) requests.  With
     paced=True each request is submitted at its arrival time; otherwise all
