@@ -476,6 +476,8 @@ def main():
                     help="sweep the knobs on the workload first and use the fastest")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload (no other configs, batched or served)")
+    ap.add_argument("--configs", default=",".join(CONFIG_NAMES[:2] + CONFIG_NAMES[3:]),
+                    help="comma-separated workloads measured beside the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -567,7 +569,11 @@ def main():
     configs = {args.workload: dict(head, roofline=roof, cpu_baseline=cpu)}
     configs[args.workload].pop("kernel_s", None)
     configs[args.workload]["kernel_ms"] = seg_s * 1e3
-    if not args.no_extras:
+    extra = set() if args.no_extras else {c.strip() for c in args.configs.split(",") if c.strip()}
+    unknown = extra - set(CONFIG_NAMES)
+    if unknown:
+        raise SystemExit("unknown workloads: %s" % ", ".join(sorted(unknown)))
+    if "odd_below_2pow22" in extra:
         import numpy as np
 
         import oracle
@@ -590,6 +596,7 @@ def main():
         del r1
         configs["odd_below_2pow22"] = dict(c1, roofline=l1, cpu_baseline=cpu1)
 
+    if "odd_2pow31_at_2pow40" in extra:
         a, b = workloads.CONFIGS["odd_2pow31_at_2pow40"]
         log("odd_2pow31_at_2pow40")
         c2, _ = run_range(a, b, 20, max(args.warmup, 1), args.streams)
@@ -600,6 +607,7 @@ def main():
                                "seeded random odd n of the workload interval", host)
         configs["odd_2pow31_at_2pow40"] = dict(c2, roofline=l2, cpu_baseline=cpu2)
 
+    if "batch_4096_intervals" in extra:
         log("batch_4096_intervals")
         c4, (blo, bhi) = bench_batched(5, ceil)
         if not args.no_cpu_baseline:
@@ -608,6 +616,7 @@ def main():
                 nthreads, "seeded odd n, 64 per interval", host)
         configs["batch_4096_intervals"] = c4
 
+    if "served_poisson_2000" in extra:
         log("served_poisson_2000 (11 s paced, then unpaced, then plain)")
         c5, reqs = bench_served(ceil)
         if not args.no_cpu_baseline:

@@ -247,6 +247,9 @@ void esq_batch_destroy(esq_batch *batch);
  *                later-launched quarter of the workgroups, in units of 64
  *                clocks (0..4096; 0 = none; default 72, about a quarter of a
  *                segment at seg_log2 18)
+ *   "cof_weight" large primes: the cost of one cofactor-enumeration thread in
+ *                percent of one first-hit thread, in the per-launch choice of
+ *                the cut-over between the two (1..10000)
  *   "priority"   segment kernel: 1 = raise the wave priority of workgroups
  *                with more of their run left (default), 0 = off
  * Applies to calls made after it.  Returns ESQ_EINVAL for an unknown name

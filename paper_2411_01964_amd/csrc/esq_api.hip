@@ -60,6 +60,7 @@ struct Params {
     int64_t runs_per_wg = 1;    // one interval: runs per resident workgroup
     int64_t stagger = 72;       // segment kernel: start delay per workgroup slot (x 64 clocks)
     int64_t priority = 1;       // segment kernel: wave priority from the share of the run left
+    int64_t cof_weight = 60;    // large primes: cost of a cofactor thread, % of a first-hit thread
 };
 
 struct MedTable {
@@ -75,8 +76,10 @@ struct Ctx {
     uint64_t plimit = 0;            // every odd prime <= plimit is in `primes`
     std::vector<uint32_t> primes;   // odd primes ascending (3, 5, 7, ...)
     std::vector<double> inv_pref;   // inv_pref[i] = sum over t < i of 1 / primes[t]^2
-    uint32_t* d_primes = nullptr;   // the primes, then their coarse index
+    uint32_t* d_primes = nullptr;   // the primes, their coarse index, Barrett reciprocals
     uint32_t pidx_n = 0;
+    size_t qinv_at = 0;             // offset (uint32 units) of the reciprocals in d_primes
+    uint32_t n_qinv = 0;            // primes[0 .. n_qinv) have one
     uint64_t* d_wheel = nullptr;
     unsigned long long* d_phase = nullptr;  // phase-clock counters, at the end of the d_wheel allocation
     uint64_t* d_wheel2 = nullptr;
@@ -487,7 +490,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
             const uint32_t de = std::max(med_end, prime_upper(c, cand));
             const double n_direct = (double)(de - med_end);
             const double n_cofac = (double)m_hi_max / ((double)cand * (double)cand) / 2;
-            const double cost = n_direct + 0.6 * n_cofac;
+            const double cost = n_direct + 0.01 * (double)par.cof_weight * n_cofac;
             if (h == 20 || cost < best) {
                 best = cost;
                 P0 = cand;
@@ -667,6 +670,8 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.primes = c->d_primes;
     L.pidx = c->d_primes + c->primes.size();
     L.pidx_n = c->pidx_n;
+    L.qinv = reinterpret_cast<const uint64_t*>(c->d_primes + c->qinv_at);
+    L.n_qinv = c->n_qinv;
     L.medq = mt ? mt->medq : nullptr;
     L.tasks = mt ? mt->tasks : nullptr;
     L.wheel = c->d_wheel;
@@ -936,7 +941,21 @@ int esq_init(int device, uint64_t max_hi)
                 i++;
             idx[v] = i;
         }
+        // Barrett reciprocals floor(2^64 / p^2) of the primes the large-prime
+        // pass reduces by (p <= kCofactorPrime), 8-byte aligned after the index
+        const size_t n_main = pr.size();
+        const uint32_t n_qinv = (uint32_t)(std::upper_bound(pr.begin(), pr.end(),
+                                                            (uint32_t)kCofactorPrime) - pr.begin());
         pr.insert(pr.end(), idx.begin(), idx.end());
+        if (pr.size() & 1)
+            pr.push_back(0);
+        const size_t qinv_at = pr.size();  // in uint32 units
+        for (uint32_t i = 0; i < n_qinv; i++) {
+            const uint64_t q = (uint64_t)pr[i] * pr[i];
+            const uint64_t m = (uint64_t)(((unsigned __int128)1 << 64) / q);
+            pr.push_back((uint32_t)m);
+            pr.push_back((uint32_t)(m >> 32));
+        }
         uint32_t* d = nullptr;
         e = hipMalloc(&d, pr.size() * 4);
         if (e != hipSuccess)
@@ -945,7 +964,9 @@ int esq_init(int device, uint64_t max_hi)
             (void)hipFree(d);
             return hip_fail(e, "hipMemcpy(primes)");
         }
-        pr.resize(pr.size() - pidx_n);
+        pr.resize(n_main);
+        c->qinv_at = qinv_at;
+        c->n_qinv = n_qinv;
         if (c->d_primes) {
             (void)hipDeviceSynchronize();
             (void)hipFree(c->d_primes);
@@ -1276,6 +1297,10 @@ int esq_set_param(const char* name, int64_t value)
         if (value < 0 || value > 4096)
             return fail(ESQ_EINVAL, "stagger out of range");
         g_par.stagger = value;
+    } else if (n == "cof_weight") {
+        if (value < 1 || value > 10000)
+            return fail(ESQ_EINVAL, "cof_weight out of range");
+        g_par.cof_weight = value;
     } else if (n == "priority") {
         if (value < 0 || value > 1)
             return fail(ESQ_EINVAL, "priority must be 0 or 1");
@@ -1312,6 +1337,7 @@ int64_t esq_get_param(const char* name)
     if (n == "runs_per_wg") return g_par.runs_per_wg;
     if (n == "stagger") return g_par.stagger;
     if (n == "priority") return g_par.priority;
+    if (n == "cof_weight") return g_par.cof_weight;
     return -1;
 }
 

@@ -86,6 +86,8 @@ struct Launch {
     const uint32_t* primes;       // odd primes ascending
     const uint32_t* pidx;         // pidx[v]: index of the first prime >= v << kPidxShift
     uint32_t pidx_n;              // entries of pidx
+    const uint64_t* qinv;         // qinv[i] = floor(2^64 / primes[i]^2) for i < n_qinv
+    uint32_t n_qinv;              // every prime <= kCofactorPrime has one
     const uint2* medq;            // per medium prime: (q, S mod q)
     const uint2* tasks;           // medium-prime lane-tasks
     uint32_t tasks_in_lds;        // 1: the task table is copied into LDS

@@ -125,6 +125,25 @@ __device__ __forceinline__ uint64_t first_hit(int64_t B0, uint64_t q)
     return (uint64_t)f;
 }
 
+// x mod q for any x < 2^64 by Barrett reduction (Barrett, CRYPTO '86): with
+// m = floor(2^64 / q), t = floor(x m / 2^64) is floor(x / q) or one less, so
+// x - t q lies in [0, 2q) and one conditional subtraction finishes it
+__device__ __forceinline__ uint64_t mod_barrett(uint64_t x, uint64_t q, uint64_t m)
+{
+    const uint64_t r = x - __umul64hi(x, m) * q;
+    return r >= q ? r - q : r;
+}
+
+// first_hit with the prime's Barrett reciprocal m = floor(2^64 / q)
+__device__ __forceinline__ uint64_t first_hit_b(int64_t B0, uint64_t q, uint64_t m)
+{
+    const int64_t h = (int64_t)((q - 1) >> 1);
+    if (B0 <= h)
+        return mod_barrett((uint64_t)(h - B0), q, m);
+    const uint64_t r = mod_barrett((uint64_t)(B0 - h), q, m);
+    return r ? q - r : 0;
+}
+
 __device__ __forceinline__ uint64_t isqrt_floor(uint64_t x)
 {
     uint64_t r = (uint64_t)sqrt((double)x);
@@ -183,7 +202,8 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
             return;
         const uint64_t p = L.primes[pi];
         const uint64_t q = p * p;
-        for (uint64_t y = first_hit(B0, q) + g * q; y < E; y += kHeavyLanes * q)
+        const uint64_t f = pi < L.n_qinv ? first_hit_b(B0, q, L.qinv[pi]) : first_hit(B0, q);
+        for (uint64_t y = f + g * q; y < E; y += kHeavyLanes * q)
             bucket_emit(L, iv, y);
         return;
     }
@@ -194,7 +214,8 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
             return;
         const uint64_t p = L.primes[pi];
         const uint64_t q = p * p;
-        for (uint64_t y = first_hit(B0, q); y < E; y += q)
+        const uint64_t f = pi < L.n_qinv ? first_hit_b(B0, q, L.qinv[pi]) : first_hit(B0, q);
+        for (uint64_t y = f; y < E; y += q)
             bucket_emit(L, iv, y);
         return;
     }

@@ -11,7 +11,7 @@ from tests.conftest import load_oracle_sample
 
 pytestmark = pytest.mark.gpu
 DEFAULTS = dict(seg_log2=18, kh=13, block=512, entry_hits=12, tail_cap=1 << 20,
-                medium_max=4095, bucket_cap=0, items_per_wg=4)
+                medium_max=4095, bucket_cap=0, items_per_wg=4, cof_weight=60)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -43,7 +43,8 @@ def mixed_intervals(seed, count, log2_len=(4, 17)):
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(seg_log2=12, items_per_wg=1), dict(kh=4),
-                                 dict(bucket_cap=1, medium_max=101)])
+                                 dict(bucket_cap=1, medium_max=101), dict(cof_weight=1),
+                                 dict(cof_weight=10000)])
 def test_batch_equals_alone(kw):
     for k, v in DEFAULTS.items():
         esq.set_param(k, kw.get(k, v))
