@@ -83,6 +83,8 @@ struct Ctx {
     uint64_t* d_wheel = nullptr;
     unsigned long long* d_phase = nullptr;  // phase-clock counters, at the end of the d_wheel allocation
     uint64_t* d_wheel2 = nullptr;
+    uint64_t* d_wheel_s = nullptr;  // the two tables one position lower (search regions)
+    uint64_t* d_wheel2_s = nullptr;
     hipMemPool_t pool = nullptr;    // per-call scratch: stream-ordered, kept cached
     std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
     std::map<std::tuple<int, uint32_t, size_t>, int> occupancy;  // (mode, block, LDS bytes) -> workgroups per CU
@@ -476,7 +478,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
         if (!v.nseg)
             continue;
         n_live++;
-        const int64_t B0 = v.A0 - (int64_t)hlo * 64;
+        const int64_t B0 = v.A0 - (int64_t)hlo * 64 - (mode == 2 ? 0 : 1);  // region bit 0
         const uint64_t E = (uint64_t)(v.nseg - 1) * S + R;
         m_hi_max = std::max(m_hi_max, 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1);
     }
@@ -510,7 +512,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
         pmax_end_all = std::max(pmax_end_all, v.pmax_end);
         v.b_direct_end = std::max(med_end, std::min(v.pmax_end, direct_end));
         if (v.pmax_end > v.b_direct_end) {
-            const int64_t B0 = v.A0 - (int64_t)hlo * 64;
+            const int64_t B0 = v.A0 - (int64_t)hlo * 64 - (mode == 2 ? 0 : 1);  // region bit 0
             const uint64_t E = (uint64_t)(v.nseg - 1) * S + R;
             const uint64_t m_hi = 2 * (uint64_t)(B0 + (int64_t)E - 1) + 1;
             const uint64_t pc = c->primes[v.b_direct_end];  // least cofactor-path prime
@@ -674,8 +676,12 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     L.n_qinv = c->n_qinv;
     L.medq = mt ? mt->medq : nullptr;
     L.tasks = mt ? mt->tasks : nullptr;
-    L.wheel = c->d_wheel;
-    L.wheel2 = c->d_wheel2;
+    // search modes: a region's bit 0 is the odd index one below its word
+    // boundary, so that a word of n-bits lines up with the bits of their
+    // first candidates n - 2 (the search's first window needs no shift)
+    L.origin = mode == 2 ? 0u : 1u;
+    L.wheel = mode == 2 ? c->d_wheel : c->d_wheel_s;
+    L.wheel2 = mode == 2 ? c->d_wheel2 : c->d_wheel2_s;
     L.tail_cap = tail_cap;
     P->mode = mode;
     P->n_heavy = n_heavy;
@@ -903,14 +909,14 @@ int esq_init(int device, uint64_t max_hi)
         (void)hipMemPoolSetAttribute(g_ctx->pool, hipMemPoolAttrReleaseThreshold, &keep);
         // both tables in one 2 MiB allocation (a single large page for the
         // translation caches of every CU)
-        static_assert((kWheelPeriod + kWheelExtra + kWheel2Period + kWheelExtra) * 8 <= kWheelAlloc,
-                      "wheel tables exceed their allocation");
-        static_assert((kWheelPeriod + kWheelExtra + kWheel2Period + kWheelExtra) * 8 + kPhaseSlots * 8 <=
+        static_assert(2 * (kWheelPeriod + kWheelExtra + kWheel2Period + kWheelExtra) * 8 + kPhaseSlots * 8 <=
                           kWheelAlloc,
-                      "phase counters exceed the wheel allocation");
+                      "wheel tables and phase counters exceed their allocation");
         e = hipMalloc(&g_ctx->d_wheel, kWheelAlloc);
         if (e == hipSuccess) {
             g_ctx->d_wheel2 = g_ctx->d_wheel + (kWheelPeriod + kWheelExtra);
+            g_ctx->d_wheel_s = g_ctx->d_wheel2 + (kWheel2Period + kWheelExtra);
+            g_ctx->d_wheel2_s = g_ctx->d_wheel_s + (kWheelPeriod + kWheelExtra);
             g_ctx->d_phase = reinterpret_cast<unsigned long long*>(g_ctx->d_wheel) + (kWheelAlloc / 8 - kPhaseSlots);
             e = hipMemset(g_ctx->d_phase, 0, kPhaseSlots * 8);
         }
@@ -919,7 +925,8 @@ int esq_init(int device, uint64_t max_hi)
             g_ctx = nullptr;
             return fail(ESQ_ENOMEM, "hipMalloc(wheel)");
         }
-        if ((e = launch_wheel_build(g_ctx->d_wheel, g_ctx->d_wheel2, nullptr)) != hipSuccess) {
+        if ((e = launch_wheel_build(g_ctx->d_wheel, g_ctx->d_wheel2, 0, nullptr)) != hipSuccess ||
+            (e = launch_wheel_build(g_ctx->d_wheel_s, g_ctx->d_wheel2_s, 1, nullptr)) != hipSuccess) {
             free_ctx(g_ctx);
             g_ctx = nullptr;
             return hip_fail(e, "k_wheel_build");

@@ -25,7 +25,7 @@ namespace esq {
 constexpr uint32_t kWheelPeriod = 9u * 25u * 49u;  // 11025 words: the table stays in L2
 constexpr uint32_t kWheelExtra = 16640;   // >= largest region in 64-bit words
 constexpr uint32_t kWheel2Period = 121u * 169u;  // 20449 words: second table (11^2, 13^2)
-constexpr size_t kWheelAlloc = 2u << 20;  // bytes holding both tables
+constexpr size_t kWheelAlloc = 2u << 20;  // bytes holding both tables, at both origins
 constexpr uint32_t kFirstMedium = 5;      // primes[0 .. 5) = 3, 5, 7, 11, 13: the two tables
 constexpr int kMaxKh = 13;                // deepest in-LDS level supported
 constexpr int kMaxMedium = 1536;          // medium primes per launch (LDS offsets)
@@ -96,6 +96,8 @@ struct Launch {
     unsigned long long* phase;    // non-null: per-phase clock ticks of the segment loop (init, marking, search or store, segments)
     const uint64_t* wheel;        // kWheelPeriod + kWheelExtra words (9, 25, 49)
     const uint64_t* wheel2;       // kWheel2Period + kWheelExtra words (121, 169)
+    uint32_t origin;              // 1: a region's bit 0 is the odd index one below its word
+                                  // boundary (search modes; wheel tables shifted to match)
     uint32_t* bucket_cnt;         // per global segment
     uint32_t* bucket_slot;        // bucket_cap per global segment
     unsigned int* queue;          // work-queue head
@@ -107,7 +109,7 @@ struct Launch {
 };
 
 // launchers (esq_kernels.hip); all return hipError_t of the launch
-hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, hipStream_t s);
+hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, uint32_t shift, hipStream_t s);
 hipError_t launch_prepare(const Launch& L, Acc* accs, const Interval* iv_single,
                           uint32_t nseg_total, hipStream_t s);
 hipError_t launch_bucket(const Launch& L, uint32_t n_heavy, uint32_t max_direct, uint32_t max_cof,

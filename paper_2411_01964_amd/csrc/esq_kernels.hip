@@ -29,8 +29,10 @@ namespace esq {
 // pattern repeats every `period` words when gcd(64, period) = 1: 9 * 25 * 49
 // for the first table, 121 * 169 for the second.  Both tables carry
 // kWheelExtra more words so that a region never wraps; together they take
-// about 0.5 MB and stay in L2.
-__global__ void k_wheel_build(uint64_t* wheel, uint64_t* wheel2)
+// about 0.5 MB and stay in L2.  A second pair of tables holds the same
+// patterns one position lower (word w: odd indices 64w - 1 .. 64w + 62), for
+// the search's regions, whose bit 0 sits one position below a word boundary.
+__global__ void k_wheel_build(uint64_t* wheel, uint64_t* wheel2, uint32_t shift)
 {
     const uint32_t n1 = kWheelPeriod + kWheelExtra, n2 = kWheel2Period + kWheelExtra;
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < n1 + n2;
@@ -38,7 +40,7 @@ __global__ void k_wheel_build(uint64_t* wheel, uint64_t* wheel2)
         const bool second = w >= n1;
         const uint32_t ww = second ? w - n1 : w;
         const uint32_t period = second ? kWheel2Period : kWheelPeriod;
-        const uint32_t base = (uint32_t)(((uint64_t)ww * 64u) % period);
+        const uint32_t base = (uint32_t)(((uint64_t)ww * 64u + period - shift) % period);
         uint64_t word = 0;
         for (uint32_t b = 0; b < 64; b++) {
             const uint32_t x = base + b;
@@ -54,9 +56,9 @@ __global__ void k_wheel_build(uint64_t* wheel, uint64_t* wheel2)
     }
 }
 
-hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, hipStream_t s)
+hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, uint32_t shift, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_wheel_build, dim3(1024), dim3(256), 0, s, wheel, wheel2);
+    hipLaunchKernelGGL(k_wheel_build, dim3(1024), dim3(256), 0, s, wheel, wheel2, shift);
     return hipGetLastError();
 }
 
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(256) void k_bucket(Launch L, uint32_t n_heavy, uint
 {
     const Interval iv = L.iv[blockIdx.y];
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t B0 = iv.A0 - (int64_t)L.hlo_words * 64;
+    const int64_t B0 = iv.A0 - (int64_t)L.hlo_words * 64 - (int64_t)L.origin;  // region bit 0
     const uint64_t S = 1ull << L.log2S;
     const uint64_t E = (uint64_t)(iv.nseg ? iv.nseg - 1 : 0) * S + (uint64_t)L.rw * 64;
     if (iv.nseg == 0)
@@ -614,7 +616,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 else
                     __builtin_amdgcn_s_setprio(3);
             }
+            // the region's words start at odd index Bs (a multiple of 64) for
+            // the wheel tables (at the launch's origin); its bit 0 is odd index
+            // B1 = Bs - origin
             const int64_t Bs = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S;
+            const int64_t B1 = Bs - (int64_t)L.origin;
             const int64_t gw0 = Bs / 64;  // exact: Bs is a multiple of 64
             const uint32_t wb = (uint32_t)(((uint64_t)IV.wheel_base0 + (uint64_t)seg * wstep) % kWheelPeriod);
 
@@ -674,17 +680,25 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         *reinterpret_cast<const uint64_t*>(src + o) |
                         *reinterpret_cast<const uint64_t*>(src2 + o);
                 }
+                // at origin 1 a region whose first word starts at odd index 0
+                // has bit 0 at odd index -1, not positive: marked (thread 0
+                // wrote word 0 itself)
+                if (gw0 == 0 && L.origin && tid == 0)
+                    bm[0] |= 1ull;
             } else {
+                // words below odd index 0 are all marked; at origin 1 the word
+                // at index 0 starts with odd index -1, marked too
                 for (uint32_t w = tid; w < L.rw; w += T)
                     bm[w] = (gw0 + (int64_t)w < 0)
                                 ? ~0ull
                                 : (reinterpret_cast<const uint64_t*>(src)[w] |
-                                   reinterpret_cast<const uint64_t*>(src2)[w]);
+                                   reinterpret_cast<const uint64_t*>(src2)[w] |
+                                   (gw0 + (int64_t)w == 0 ? (uint64_t)L.origin : 0ull));
             }
             if (seg == seg0) {
                 for (uint32_t i = tid; i < nmed; i += T) {
                     const uint32_t q = s_medq[i].x;
-                    const int64_t d = (int64_t)((q - 1) >> 1) - Bs;
+                    const int64_t d = (int64_t)((q - 1) >> 1) - B1;
                     int64_t f = d % (int64_t)q;
                     if (f < 0)
                         f += q;
@@ -737,7 +751,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     for (uint32_t pi = L.med_end + tid; pi < IV.pmax_end; pi += T) {
                         const uint64_t p = L.primes[pi];
                         const uint64_t q = p * p;
-                        for (uint64_t pos = first_hit(Bs, q); pos < R; pos += q)
+                        for (uint64_t pos = first_hit(B1, q); pos < R; pos += q)
                             mark(bm32, (uint32_t)pos);
                     }
                 }
@@ -844,21 +858,30 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 for (int k = 1; k <= kMaxKh; k++) {
                     if (!FAST && k > (int)klds)
                         break;
+                    // The region's bit 0 is one odd index below its first word
+                    // boundary, so bit b of a word holds the odd index one below
+                    // the word's n-bit b: n - 2^k, 2^(k-1) positions below n, is
+                    // t = 2^(k-1) - 1 bits below in the bitmap.  k = 1 reads the
+                    // word itself; k <= 7 funnel-shifts it with the word below
+                    // by t; from k = 8 on the two words d = 2^(k-7) and d - 1
+                    // below, shifted by 63.
                     uint32_t wlo, whi;
-                    if (k <= 5) {
-                        const uint32_t sh = 32u - (1u << (k - 1));
+                    if (k == 1) {
+                        wlo = clo;
+                        whi = chi;
+                    } else if (k <= 6) {
+                        const uint32_t sh = 33u - (1u << (k - 1));
                         wlo = __builtin_amdgcn_alignbit(clo, phi, sh);
                         whi = __builtin_amdgcn_alignbit(chi, clo, sh);
-                    } else if (k == 6) {
-                        wlo = phi;
-                        whi = clo;
                     } else if (k == 7) {
-                        wlo = plo;
-                        whi = phi;
+                        wlo = __builtin_amdgcn_alignbit(phi, plo, 1);
+                        whi = __builtin_amdgcn_alignbit(clo, phi, 1);
                     } else {
-                        const uint64_t x = (ulo | uhi) ? pw[1 - (1 << (k - 7))] : 0ull;
-                        wlo = (uint32_t)x;
-                        whi = (uint32_t)(x >> 32);
+                        const bool any = (ulo | uhi) != 0;
+                        const uint64_t y = any ? pw[1 - (1 << (k - 7))] : 0ull;
+                        const uint64_t x = any ? pw[2 - (1 << (k - 7))] : 0ull;
+                        wlo = __builtin_amdgcn_alignbit((uint32_t)(y >> 32), (uint32_t)y, 1);
+                        whi = __builtin_amdgcn_alignbit((uint32_t)x, (uint32_t)(y >> 32), 1);
                     }
                     ulo &= wlo;
                     uhi &= whi;

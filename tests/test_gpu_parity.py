@@ -325,3 +325,19 @@ def test_kmax_at_most_kh_needs_no_tail_list(kmax):
     knobs()
     e = esq.verify_range(lo, hi, kmax=kmax, exceptions_cap=64)
     assert e["exceptions"] == o["exceptions"][:64]
+
+
+@pytest.mark.parametrize("kh,seg_log2", [(13, 18), (8, 12), (4, 10), (13, 10)])
+def test_region_origin_near_zero(kh, seg_log2):
+    """The search's regions start one odd index below a word boundary: the
+    region whose first word starts at odd index 0 (its bit 0 is odd index -1,
+    not positive) and the regions below 0, against the oracle, per n, at
+    several halo depths."""
+    knobs(kh=kh, seg_log2=seg_log2)
+    halo = (1 << (kh - 1)) if kh >= 7 else 64
+    for lo, hi in ((2 * halo + 1, 2 * halo + 1 + 2 * 5000), (1, 2 * halo + 2 * 3000),
+                   (2 * halo - 63, 2 * halo + 2 * 700)):
+        g = esq.verify_range(lo, hi, per_n=True, exceptions_cap=64)
+        o = oracle.verify_range(lo, hi, per_n=True)
+        assert_same(g, o)
+    knobs()
