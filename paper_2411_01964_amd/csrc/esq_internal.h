@@ -64,8 +64,9 @@ struct Interval {
     uint32_t n_cof_wide;    // the first n_cof_wide cofactors (widest ranges) take 8 lanes each
 };
 
-// Medium-prime lane-task, packed in a uint2: x = idx | (v << 16), y = c;
-// it marks f + (v + c t) q, t >= 0, of medium prime idx (0 = the prime 17).
+// Medium-prime lane-task, packed in a uint2: x = v q | (idx << 21), y = c q;
+// it marks f + v q + t c q, t >= 0, of medium prime idx (0 = the prime 17),
+// f its first hit in the region.
 
 // Geometry and resources shared by every interval of a launch.
 struct Launch {

@@ -718,17 +718,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             //    from the segment's hit slots (directly if the slots overflowed)
             // A prime with h = ceil(R / q) hits per region has c <= h tasks, so
             // c q <= R + q and f + v q < R + q: 32-bit positions suffice.
-            // v > 0 and c > 1 only when q < R < 2^21, and then c q <= R + q;
-            // with q clamped to 2^23 (> R: a prime with q > R has c = 1, v = 0
-            // and at most one hit, after which pos + step > R) both products
-            // fit 24-bit operands: full-rate 24-bit multiplies
+            // a task carries its start past the prime's first hit (v q, 21
+            // bits), the prime's index (11 bits) and its step c q: one LDS read
+            // of the prime's offset, no multiply
             auto mark_tasks = [&](const uint2* tk_table) {
                 for (uint32_t e = tid; e < L.n_tasks; e += T) {
                     const uint2 tk = tk_table[e];
-                    const uint32_t idx = tk.x & 0xffffu, v = tk.x >> 16, c = tk.y;
-                    const uint32_t q = min(s_medq[idx].x, 1u << 23);
-                    const uint32_t step = __umul24(c, q);
-                    for (uint32_t pos = s_f[idx] + __umul24(v, q); pos < R; pos += step)
+                    const uint32_t idx = tk.x >> 21, step = tk.y;
+                    for (uint32_t pos = s_f[idx] + (tk.x & 0x1fffffu); pos < R; pos += step)
                         mark(bm32, pos);
                 }
             };
