@@ -599,7 +599,7 @@ def main():
     if "odd_2pow31_at_2pow40" in extra:
         a, b = workloads.CONFIGS["odd_2pow31_at_2pow40"]
         log("odd_2pow31_at_2pow40")
-        c2, _ = run_range(a, b, 20, max(args.warmup, 1), args.streams)
+        c2, _ = run_range(a, b, 100, max(args.warmup, 6), args.streams)
         l2, _ = rooflines(c2["n_odd"], c2.pop("kernel_s"), ceil, "k_segment")
         cpu2 = None
         if not args.no_cpu_baseline:
