@@ -311,7 +311,7 @@ def bench_per_n(lo, hi, n_odd, ref, steps=5):
     esq.set_param("profile", 0)
     k_s = seg_ms / max(launches, 1) / 1e3
     return {"odd_n_per_s": n_odd / wall, "ms_per_call": wall * 1e3, "kernel_ms": k_s * 1e3,
-            "kernel_odd_n_per_s": n_odd / k_s,
+            "kernel_odd_n_per_s": n_odd / k_s, "block": esq.get_param("per_n_block"),
             "roofline": {"bound": "hbm", "achieved": n_odd / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
                          "frac": n_odd / k_s / HBM_PEAK, "traffic": None,
                          "kernel": "k_segment (per-n)"}}
@@ -340,7 +340,8 @@ def bench_sieve(lo, hi, steps=5):
     k_s = seg_ms / max(launches, 1) / 1e3
     del w
     return {"odd_m_per_s": n / wall, "ms_per_call": wall * 1e3, "kernel_ms": k_s * 1e3,
-            "kernel_odd_m_per_s": n / k_s,
+            "kernel_odd_m_per_s": n / k_s, "block": esq.get_param("sieve_block"),
+            "seg_log2": esq.get_param("sieve_seg_log2"),
             "roofline": {"bound": "hbm", "achieved": out_bytes / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
                          "frac": out_bytes / k_s / HBM_PEAK, "traffic": None,
                          "kernel": "k_segment (sieve)"}}
@@ -525,6 +526,7 @@ def main():
                 "valu_alignbit_Tops": ceil["valu_alignbit_ops_per_s"] / 1e12,
                 "valu_bcnt_Tops": ceil["valu_bcnt_ops_per_s"] / 1e12,
                 "l2_read_GBps": ceil["l2_read_Bps"] / 1e9,
+                "hbm_write_GBps": ceil["hbm_write_Bps"] / 1e9,
                 "nominal_lds_GBps": LDS_PEAK / 1e9, "nominal_valu_Tops": VALU_PEAK / 1e12}
 
     # ---- the headline workload
@@ -562,9 +564,11 @@ def main():
     log("per-n mode: %d bytes per call" % n_odd)
     per_n = bench_per_n(lo, hi, n_odd, ref)
     per_n["roofline"]["traffic"] = traffic.get("per_n")
+    per_n["roofline"]["frac_of_write_ceiling"] = per_n["roofline"]["achieved"] * 1e9 / ceil["hbm_write_Bps"]
     log("sieve alone: %d bits per call" % n_odd)
     sieve = bench_sieve(lo, hi)
     sieve["roofline"]["traffic"] = traffic.get("sieve")
+    sieve["roofline"]["frac_of_write_ceiling"] = sieve["roofline"]["achieved"] * 1e9 / ceil["hbm_write_Bps"]
 
     configs = {args.workload: dict(head, roofline=roof, cpu_baseline=cpu)}
     configs[args.workload].pop("kernel_s", None)

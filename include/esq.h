@@ -225,11 +225,15 @@ void esq_batch_destroy(esq_batch *batch);
 /*
  * Tuning knobs (results never depend on them; only speed does).  Names:
  *   "seg_log2"   log2 of the segment length in odd numbers held in LDS (10..20)
- *   "sieve_seg_log2" the same for esq_sieve_segment (default one larger: its
- *                bitmap stores do not overlap the next segment's sieving)
+ *   "sieve_seg_log2" the same for esq_sieve_segment (default 20: one
+ *                workgroup per CU whose storer waves write the bitmap while
+ *                its loader waves start the next segment)
  *   "kh"         deepest k resolved from the LDS bitmap (1..13); deeper k go
  *                to the exact tail pass
- *   "block"      threads per workgroup of the segment kernel (64..1024, x64)
+ *   "block"      threads per workgroup of the segment kernel, summary mode
+ *                (64..1024, x64; default 512)
+ *   "per_n_block" the same in per-n mode (default 1024)
+ *   "sieve_block" the same for esq_sieve_segment (default 1024)
  *   "entry_hits" target marks per lane-task for medium primes (1..4096)
  *   "tail_cap"   capacity of the per-call list of n unresolved in LDS
  *   "profile"    1 = time each segment-kernel launch (esq_profile_take)
@@ -282,16 +286,18 @@ int esq_phase_take(uint64_t *ticks);
 /*
  * Measured ceilings of the current device, for the rooflines of the segment
  * kernel (Section 3's sieve is LDS work, its search VALU work, the pattern
- * init L2 reads): microbenchmarks of conflict-free LDS operations, of int32
- * VALU issue and of L2 reads, eight 256-thread workgroups per CU, best of
- * three timed launches each.  out (host, ESQ_CEILINGS doubles) receives:
+ * init L2 reads, the per-n and sieve outputs HBM writes): microbenchmarks of
+ * conflict-free LDS operations, of int32 VALU issue, of L2 reads and of HBM
+ * writes, eight 256-thread workgroups per CU, best of three timed launches
+ * each.  out (host, ESQ_CEILINGS doubles) receives:
  * [0] ds_write_b64 bytes/s, [1] ds_read_b64 bytes/s, [2] ds_or_b32 bytes/s,
  * int32 VALU lane-operations/s of [3] v_add_u32/v_xor_b32, [4] v_alignbit_b32,
- * [5] v_bcnt_u32_b32, and [6] L2 read bytes/s of 16-byte loads over a 1 MiB
- * buffer.  Synchronous; allocates and frees small device buffers.  Returns
+ * [5] v_bcnt_u32_b32, [6] L2 read bytes/s of 16-byte loads over a 1 MiB
+ * buffer, and [7] HBM write bytes/s of 16-byte stores streaming over 2 GiB.
+ * Synchronous; allocates and frees device buffers (2 GiB at most).  Returns
  * ESQ_EINVAL for a null pointer, ESQ_ENOMEM or ESQ_EHIP on a HIP failure.
  */
-#define ESQ_CEILINGS 7
+#define ESQ_CEILINGS 8
 int esq_measure_ceilings(double *out);
 
 /* Message for the last non-zero return on the calling thread ("" if none). */

@@ -47,9 +47,11 @@ int hip_fail(hipError_t e, const char* what)
 
 struct Params {
     int seg_log2 = 18;
-    int sieve_seg_log2 = 19;  // Algorithm 1 alone: fewer, longer segments (its stores do not overlap)
+    int sieve_seg_log2 = 20;  // Algorithm 1 alone: one workgroup per CU, loader and storer waves
     int kh = 13;
-    int block = 512;
+    int block = 512;          // segment kernel, summary mode
+    int per_n_block = 1024;   // per-n mode: more waves in flight behind the byte stores
+    int sieve_block = 1024;   // Algorithm 1 alone: likewise behind the bitmap stores
     int entry_hits = 12;
     int64_t tail_cap = 1 << 20;
     int profile = 0;
@@ -373,9 +375,16 @@ uint32_t medium_end(const Ctx* c, const Params& par)
     return std::min<uint32_t>(e, kFirstMedium + (uint32_t)kMaxMedium);
 }
 
-// The medium-prime tables of the verify geometry for the current knobs, made
-// at set-up (esq_init, esq_set_param; g_mu held) so that calls find them
-// resident.
+// Threads per workgroup of the segment kernel in a mode (0 summary, 1 per-n,
+// 2 sieve alone).
+uint32_t block_for(const Params& par, int mode)
+{
+    return (uint32_t)(mode == 0 ? par.block : mode == 1 ? par.per_n_block : par.sieve_block);
+}
+
+// The medium-prime tables of the verify geometry for the current knobs (at
+// the summary and the per-n block size), made at set-up (esq_init,
+// esq_set_param; g_mu held) so that calls find them resident.
 int prebuild_med_table(Ctx* c, const Params& par)
 {
     const uint32_t med_end = medium_end(c, par);
@@ -384,8 +393,13 @@ int prebuild_med_table(Ctx* c, const Params& par)
     const uint32_t hlo = (par.kh >= 7 ? (1u << (par.kh - 1)) : 64u) / 64;
     const uint32_t rw = hlo + (uint32_t)((1ull << par.seg_log2) / 64);
     MedTable* mt = nullptr;
-    return get_med_table_locked(c, rw, (uint32_t)par.seg_log2, med_end, (uint32_t)par.entry_hits,
-                                (uint32_t)par.block, &mt);
+    for (int mode = 0; mode < 2; mode++) {
+        const int rc = get_med_table_locked(c, rw, (uint32_t)par.seg_log2, med_end, (uint32_t)par.entry_hits,
+                                            block_for(par, mode), &mt);
+        if (rc)
+            return rc;
+    }
+    return ESQ_OK;
 }
 
 // One interval to process, in odd-index terms: verify -> the n-indices
@@ -415,6 +429,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
 {
     const uint32_t n_iv = (uint32_t)reqs.size();
     const uint32_t log2S = (uint32_t)(mode == 2 ? par.sieve_seg_log2 : par.seg_log2);
+    const uint32_t blk = block_for(par, mode);
     const uint64_t S = 1ull << log2S;
     const uint32_t SW = (uint32_t)(S / 64);
     const uint32_t kmax_eff = kmax ? kmax : 63;
@@ -557,12 +572,12 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
             // only a table made at set-up: making one here would allocate
             std::lock_guard<std::mutex> lk(g_mu);
             auto it = c->med.find(std::make_tuple(rw, log2S, med_end, (uint32_t)par.entry_hits,
-                                                  (uint32_t)par.block));
+                                                  blk));
             if (it == c->med.end())
                 return fail(ESQ_ENOMEM, "medium-prime tables for these knobs are not resident");
             mt = &it->second;
         } else if ((rc = get_med_table(c, rw, log2S, med_end, (uint32_t)par.entry_hits,
-                                       (uint32_t)par.block, &mt))) {
+                                       blk, &mt))) {
             return rc;
         }
     }
@@ -581,22 +596,22 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     // LDS of the segment kernel: bitmap + medium-prime tables (+ tasks if they fit)
     const uint32_t nmed = med_end - kFirstMedium;
     const uint32_t n_tasks = mt ? mt->n_tasks : 0;
-    if (verify_lds_size(rw, nmed, 0, false, (uint32_t)par.block) > kVerifyLdsMax)
+    if (verify_lds_size(rw, nmed, 0, false, blk) > kVerifyLdsMax)
         return fail(ESQ_EINVAL, "segment too large for LDS with these medium primes");
     // per-n output is staged through LDS (1 KB contiguous per store) when the
     // staging area fits beside the bitmap
-    const bool stage = mode == 1 && verify_lds_size(rw, nmed, 0, true, (uint32_t)par.block) <= kVerifyLdsMax;
-    const size_t lds_base = verify_lds_size(rw, nmed, 0, stage, (uint32_t)par.block);
+    const bool stage = mode == 1 && verify_lds_size(rw, nmed, 0, true, blk) <= kVerifyLdsMax;
+    const size_t lds_base = verify_lds_size(rw, nmed, 0, stage, blk);
     auto occupancy = [&](size_t bytes) {
         std::lock_guard<std::mutex> lk(g_mu);
-        const auto key = std::make_tuple(mode, (uint32_t)par.block, bytes);
+        const auto key = std::make_tuple(mode, blk, bytes);
         auto it = c->occupancy.find(key);
         if (it == c->occupancy.end())
-            it = c->occupancy.emplace(key, verify_occupancy(mode, (uint32_t)par.block, bytes)).first;
+            it = c->occupancy.emplace(key, verify_occupancy(mode, blk, bytes)).first;
         return it->second;
     };
     // the task table goes into LDS when it fits and costs no resident workgroup
-    const size_t lds_with = verify_lds_size(rw, nmed, n_tasks, stage, (uint32_t)par.block);
+    const size_t lds_with = verify_lds_size(rw, nmed, n_tasks, stage, blk);
     const bool tasks_in_lds = n_tasks == 0 || (lds_with <= kVerifyLdsMax &&
                                                occupancy(lds_with) >= occupancy(lds_base));
     const size_t lds_bytes = tasks_in_lds ? lds_with : lds_base;
@@ -701,7 +716,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
     P->any_bucket = any_bucket;
     P->nseg_total = nseg_total;
     P->grid = (uint32_t)std::min<uint64_t>(n_items, resident);
-    P->block = (uint32_t)par.block;
+    P->block = blk;
     return ESQ_OK;
 }
 
@@ -1275,10 +1290,10 @@ int esq_set_param(const char* name, int64_t value)
         if (value < 1 || value > kMaxKh)
             return fail(ESQ_EINVAL, "kh out of range");
         g_par.kh = (int)value;
-    } else if (n == "block") {
+    } else if (n == "block" || n == "per_n_block" || n == "sieve_block") {
         if (value < 64 || value > 1024 || value % 64)
-            return fail(ESQ_EINVAL, "block out of range");
-        g_par.block = (int)value;
+            return fail(ESQ_EINVAL, n + " out of range");
+        (n == "block" ? g_par.block : n == "per_n_block" ? g_par.per_n_block : g_par.sieve_block) = (int)value;
     } else if (n == "entry_hits") {
         if (value < 1 || value > 4096)
             return fail(ESQ_EINVAL, "entry_hits out of range");
@@ -1327,7 +1342,7 @@ int esq_set_param(const char* name, int64_t value)
         return fail(ESQ_EINVAL, "unknown parameter " + n);
     }
     if (g_ctx && (n == "seg_log2" || n == "kh" || n == "medium_max" || n == "entry_hits" ||
-                  n == "block")) {
+                  n == "block" || n == "per_n_block")) {
         hipError_t e = hipSetDevice(g_ctx->device);
         if (e != hipSuccess)
             return hip_fail(e, "hipSetDevice");
@@ -1346,6 +1361,8 @@ int64_t esq_get_param(const char* name)
     if (n == "sieve_seg_log2") return g_par.sieve_seg_log2;
     if (n == "kh") return g_par.kh;
     if (n == "block") return g_par.block;
+    if (n == "per_n_block") return g_par.per_n_block;
+    if (n == "sieve_block") return g_par.sieve_block;
     if (n == "entry_hits") return g_par.entry_hits;
     if (n == "tail_cap") return g_par.tail_cap;
     if (n == "profile") return g_par.profile;

@@ -3,7 +3,9 @@
 // int32 VALU issue rate of full-rate operations and of the search's funnel
 // shift and popcount, and the L2 read bandwidth of 16-byte loads over an
 // L2-resident buffer (what the segment init streams from the pattern
-// tables).  Each microbenchmark runs eight 256-thread
+// tables), and the HBM write bandwidth of 16-byte stores streaming over a
+// buffer far larger than the caches (the bound of the per-n and sieve
+// outputs).  Each microbenchmark runs eight 256-thread
 // workgroups per CU (8 waves per SIMD) with the operations in inline assembly,
 // so that none is removed or merged by the compiler.
 #include <hip/hip_runtime.h>
@@ -19,8 +21,9 @@ namespace ceil {
 
 constexpr uint32_t kCeilBlock = 256;
 constexpr uint32_t kCeilLdsBytes = 16384;  // 8 operations x 256 lanes x 8 bytes
-constexpr int kCeilings = 7;
+constexpr int kCeilings = 8;
 constexpr uint32_t kCeilL2Bytes = 1u << 20;  // L2-resident buffer (each XCD's L2 holds 4 MiB)
+constexpr size_t kCeilHbmBytes = (size_t)2 << 30;  // write buffer: 8x the last-level cache
 
 // OP 0: ds_write_b64, 1: ds_read_b64, 2: ds_or_b32.  Lane l touches bytes
 // 8l .. 8l+7 (4l .. 4l+3 for ds_or_b32) of each 2 KB (1 KB) block, so every
@@ -192,6 +195,21 @@ __global__ __launch_bounds__(kCeilBlock) void k_ceil_l2(const u32x4c* buf, uint6
     sink[(size_t)blockIdx.x * kCeilBlock + tid] = (uint64_t)(acc.x ^ acc.y ^ acc.z ^ acc.w);
 }
 
+// 16-byte stores over the whole buffer: workgroup b writes its own
+// contiguous chunk of iters 4 KB blocks front to back, every store
+// instruction of a wave covering 1 KB (of the store layouts tried -- grid-
+// strided blocks, non-temporal stores, 2 to 16 workgroups per CU -- the
+// fastest on this chip).  The host sizes iters so that the gridDim chunks
+// fill the buffer exactly.
+__global__ __launch_bounds__(kCeilBlock) void k_ceil_hbm_write(u32x4c* buf, uint32_t iters)
+{
+    const uint32_t tid = threadIdx.x;
+    const u32x4c v = {tid, blockIdx.x, 0x5a5a5a5au, iters};
+    u32x4c* p = buf + (size_t)blockIdx.x * iters * kCeilBlock;
+    for (uint32_t i = 0; i < iters; i++)
+        p[(size_t)i * kCeilBlock + tid] = v;
+}
+
 }  // namespace ceil
 }  // namespace esq
 
@@ -209,6 +227,7 @@ extern "C" int esq_measure_ceilings(double* out)
     const uint32_t grid = (uint32_t)n_cu * 8u;
     uint64_t* sink = nullptr;
     u32x4c* l2buf = nullptr;
+    u32x4c* hbmbuf = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ESQ_OK;
@@ -218,14 +237,20 @@ extern "C" int esq_measure_ceilings(double* out)
         (void)hipFree(sink);
         return ESQ_ENOMEM;
     }
+    if (hipMalloc(&hbmbuf, kCeilHbmBytes) != hipSuccess) {
+        (void)hipFree(sink);
+        (void)hipFree(l2buf);
+        return ESQ_ENOMEM;
+    }
     if (hipMemset(l2buf, 0x5a, kCeilL2Bytes) != hipSuccess)
         rc = ESQ_EHIP;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rc = ESQ_EHIP;
     // bytes (or lane-operations) per thread per iteration
-    const double per_iter[kCeilings] = {64.0, 64.0, 32.0, 64.0, 64.0, 64.0, 128.0};
-    const uint32_t iters[kCeilings] = {1024, 1024, 1024, 512, 256, 256, 128};
+    const uint32_t hbm_iters = (uint32_t)(kCeilHbmBytes / ((size_t)grid * kCeilBlock * 16));
+    const double per_iter[kCeilings] = {64.0, 64.0, 32.0, 64.0, 64.0, 64.0, 128.0, 16.0};
+    const uint32_t iters[kCeilings] = {1024, 1024, 1024, 512, 256, 256, 128, hbm_iters};
     for (int t = 0; t < kCeilings && rc == ESQ_OK; t++) {
         float best = 0.f;
         for (int rep = 0; rep < 4 && rc == ESQ_OK; rep++) {
@@ -245,8 +270,10 @@ extern "C" int esq_measure_ceilings(double* out)
                 hipLaunchKernelGGL(k_ceil_valu<1>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
             else if (t == 5)
                 hipLaunchKernelGGL(k_ceil_valu<2>, dim3(grid), dim3(kCeilBlock), 0, s, sink, iters[t]);
-            else
+            else if (t == 6)
                 hipLaunchKernelGGL(k_ceil_l2, dim3(grid), dim3(kCeilBlock), 0, s, l2buf, sink, iters[t]);
+            else
+                hipLaunchKernelGGL(k_ceil_hbm_write, dim3(grid), dim3(kCeilBlock), 0, s, hbmbuf, iters[t]);
             float ms = 0.f;
             if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -267,5 +294,6 @@ extern "C" int esq_measure_ceilings(double* out)
         (void)hipStreamDestroy(s);
     (void)hipFree(sink);
     (void)hipFree(l2buf);
+    (void)hipFree(hbmbuf);
     return rc;
 }

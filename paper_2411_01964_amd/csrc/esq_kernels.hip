@@ -65,6 +65,30 @@ hipError_t launch_wheel_build(uint64_t* wheel, uint64_t* wheel2, uint32_t shift,
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Output pointers read from an Interval in memory are generic: stores through
+// them become flat stores, which also count on the LDS wait counter, so every
+// later wait for an LDS read would wait for the stores to reach memory too.
+// Stores to the output buffers go through these global-space views instead.
+typedef __attribute__((address_space(1))) uint8_t g_u8;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+typedef __attribute__((address_space(1))) u64x2 g_u64x2;
+typedef __attribute__((address_space(1))) unsigned long long g_ull;
+typedef __attribute__((address_space(1))) unsigned int g_uint;
+__device__ __forceinline__ void g_add(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_fetch_add((g_ull*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_min(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_fetch_min((g_ull*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_or(unsigned int* p, unsigned int v)
+{
+    __hip_atomic_fetch_or((g_uint*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // popcount(x) + acc in one v_bcnt_u32_b32
 __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc)
 {
@@ -304,19 +328,19 @@ __device__ __forceinline__ uint64_t valid_mask(uint64_t j0, uint64_t I0, uint64_
 // Store the 64 depth bytes D (4 per dword) of one word at out[0..63], only
 // where V has a bit.  Interior dwords that are wholly ours and valid go out
 // as aligned 32-bit stores; the rest byte by byte.
-__device__ __forceinline__ void store_depths(uint8_t* out, const uint32_t (&D)[16], uint64_t V)
+__device__ __forceinline__ void store_depths(g_u8* out, const uint32_t (&D)[16], uint64_t V)
 {
     // whole word, 16-byte aligned (every word of an interval whose first
     // n-index is a multiple of 16): four 16-byte stores
     if (V == ~0ull && ((uintptr_t)out & 15u) == 0) {
-        uint4* o = reinterpret_cast<uint4*>(out);
+        g_u32x4* o = (g_u32x4*)out;
 #pragma unroll
         for (int q = 0; q < 4; q++)
-            o[q] = make_uint4(D[4 * q], D[4 * q + 1], D[4 * q + 2], D[4 * q + 3]);
+            o[q] = u32x4{D[4 * q], D[4 * q + 1], D[4 * q + 2], D[4 * q + 3]};
         return;
     }
     const uint32_t mis = (uint32_t)((uintptr_t)out & 3u);
-    uint8_t* al = out - mis;
+    g_u8* al = out - mis;
 #pragma unroll
     for (int t = 0; t <= 16; t++) {
         // the aligned dword at al + 4t holds stream bytes 4t - mis .. 4t - mis + 3
@@ -331,7 +355,7 @@ __device__ __forceinline__ void store_depths(uint8_t* out, const uint32_t (&D)[1
             all = all && b >= 0 && b < 64 && ((V >> (b & 63)) & 1ull);
         }
         if (all) {
-            *reinterpret_cast<uint32_t*>(al + 4 * t) = val;
+            *(g_u32*)(al + 4 * t) = val;
         } else {
 #pragma unroll
             for (int i = 0; i < 4; i++) {
@@ -360,12 +384,12 @@ __device__ __forceinline__ void mark(uint32_t* bm32, uint32_t pos)
 
 // Store bytes [b0, b1) of the 16 bytes v at the 16-byte aligned p (b0, b1
 // wave-uniform): whole dwords as dwords, the rest byte by byte.
-__device__ __forceinline__ void store_part16(uint8_t* p, const u32x4 v, uint32_t b0, uint32_t b1)
+__device__ __forceinline__ void store_part16(g_u8* p, const u32x4 v, uint32_t b0, uint32_t b1)
 {
 #pragma unroll
     for (uint32_t t = 0; t < 4; t++) {
         if (4 * t >= b0 && 4 * t + 4 <= b1) {
-            *reinterpret_cast<uint32_t*>(p + 4 * t) = v[t];
+            *(g_u32*)(p + 4 * t) = v[t];
         } else {
 #pragma unroll
             for (uint32_t j = 0; j < 4; j++)
@@ -407,7 +431,7 @@ __device__ __forceinline__ u32x4 stage_shift(const u32x4 A, const u32x4 B, uint3
 // past an aligned chunk; the first and last chunks, shared with the
 // neighbouring runs, are written in part.
 template <int KQ>
-__device__ __forceinline__ void stage_store_run(u32x4* st, uint8_t* out, const uint32_t (&D)[16],
+__device__ __forceinline__ void stage_store_run(u32x4* st, g_u8* out, const uint32_t (&D)[16],
                                                 uint32_t lane, uint32_t delta)
 {
     __builtin_amdgcn_wave_barrier();
@@ -417,8 +441,8 @@ __device__ __forceinline__ void stage_store_run(u32x4* st, uint8_t* out, const u
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint8_t* g = out - delta;  // 16-byte aligned
-    u32x4* go = reinterpret_cast<u32x4*>(g);
+    g_u8* g = out - delta;  // 16-byte aligned
+    g_u32x4* go = (g_u32x4*)g;
     const uint32_t sh = (0u - delta) & 3u;
     u32x4 last;
 #pragma unroll
@@ -451,7 +475,7 @@ __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_re
 // MODE 2: Algorithm 1 alone, bitmap to HBM.  PH: the phase-clock instance
 // (measurement only).
 template <int MODE, bool PH = false>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 4 : 8))) void k_verify(Launch L)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 8 : 4))) void k_verify(Launch L)
 {
     // No static LDS: the bitmap sits at LDS address 0, so a bit position
     // turns into a word address without a base offset.
@@ -508,9 +532,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
             }
             __syncthreads();
             if (tid >= 1 && tid <= klds && s_cnt[tid])
-                atomicAdd(&acc->cnt[tid], (unsigned long long)s_cnt[tid]);
+                g_add(&acc->cnt[tid], (unsigned long long)s_cnt[tid]);
             if (tid >= 2 && tid <= klds + 1 && s_first[tid] != kNone)
-                atomicMin(&acc->first[tid], s_first[tid]);
+                g_min(&acc->first[tid], s_first[tid]);
         }
         __syncthreads();
     };
@@ -598,13 +622,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
         acc_segs += nsegs;
         const Interval IV = L.iv[ivi];
         const uint32_t cap = L.bucket_cap;
-
-        for (uint32_t seg = seg0; seg < seg0 + nsegs; seg++) {
-            phase_tick(-1);
-            // The issue arbiter favours older waves, so of the workgroups
-            // sharing a CU the first-launched would finish far ahead of the
-            // last.  Raising the priority of a workgroup with more of its run
-            // left keeps them level, and the CU busy until the end.
+        // The issue arbiter favours older waves, so of the workgroups sharing
+        // a CU the first-launched would finish far ahead of the last.  Raising
+        // the priority of a workgroup with more of its run left keeps them
+        // level, and the CU busy until the end.
+        auto set_priority = [&](uint32_t seg) {
             if (L.priority) {
                 const uint32_t q = min(((seg0 + nsegs - seg) * 4u) / nsegs, 3u);
                 if (q == 0)
@@ -616,6 +638,220 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 else
                     __builtin_amdgcn_s_setprio(3);
             }
+        };
+
+        // Algorithm 1 alone, with the waves in two roles.  A wave's vector
+        // loads and stores complete on one counter, so a wave that has stores
+        // in flight and then needs a load's result waits for the stores too;
+        // the compiler, not knowing which lanes take which branch, places
+        // such waits on every path it cannot rule out.  So the storers (upper
+        // half of the waves) run a loop of their own with no global load in
+        // it: they take the medium primes' first hits, mark, and write the
+        // bitmap out, and their stores drain while the loaders (lower half)
+        // load the next segment's tables and hit slots.  Both loops meet at
+        // the same three barriers per segment.  Needs the task table in LDS
+        // and an even number of waves.
+        constexpr uint32_t kLoadQuarters = 2;   // loader share of the waves, in quarters
+        constexpr int kLoadPairs = 2;           // table pairs per loader lane in flight
+        const bool split = MODE == 2 && L.tasks_in_lds && (T * kLoadQuarters / 4) % 64 == 0;
+        if (split) {
+            const uint32_t TL = T * kLoadQuarters / 4, TS = T - TL;
+            // wave-uniform (TL is a multiple of 64), and known to be so: each
+            // wave runs exactly one of the two loops
+            const bool loader = rfl(tid) < TL;
+            const uint64_t n_bits = IV.I1 - IV.I0;
+            const uint32_t sh = IV.out_shift;
+            auto mark_medium = [&]() {
+                for (uint32_t e = tid; e < L.n_tasks; e += T) {
+                    const uint2 tk = s_task[e];
+                    const uint32_t idx = tk.x >> 21, step = tk.y;
+                    for (uint32_t pos = s_f[idx] + (tk.x & 0x1fffffu); pos < R; pos += step)
+                        mark(bm32, pos);
+                }
+            };
+            if (loader) {
+                constexpr int kPre = 4;  // pairs per lane fetched a segment ahead
+                u64x2 pre_v[kPre], pre_x[kPre];
+                bool have_pre = false;
+                const uint32_t pairs = L.rw / 2;
+                for (uint32_t seg = seg0; seg < seg0 + nsegs; seg++) {
+                    phase_tick(-1);
+                    set_priority(seg);
+                    const int64_t Bs = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S;
+                    const int64_t B1 = Bs - (int64_t)L.origin;
+                    const int64_t gw0 = Bs / 64;
+                    const uint32_t wb = (uint32_t)(((uint64_t)IV.wheel_base0 + (uint64_t)seg * wstep) % kWheelPeriod);
+                    const uint32_t gs = IV.seg_base + seg;
+                    // the hit-slot count and first slot, then the tables (as
+                    // in the single-role loop, over the loader lanes)
+                    uint32_t nb = 0, slot_pos = R;
+                    if (L.bucket_cnt) {
+                        nb = *(const __attribute__((address_space(4))) uint32_t*)(uintptr_t)(L.bucket_cnt + gs);
+                        if (nb <= cap && tid < nb)
+                            slot_pos = L.bucket_slot[(uint64_t)gs * cap + tid];
+                    }
+                    int64_t g2 = gw0 % (int64_t)kWheel2Period;
+                    if (g2 < 0)
+                        g2 += kWheel2Period;
+                    const char* src = reinterpret_cast<const char*>(L.wheel + wb);
+                    const char* src2 = reinterpret_cast<const char*>(L.wheel2 + g2);
+                    char* dst = reinterpret_cast<char*>(bm);
+                    if (gw0 >= 0) {
+                        const uint32_t st = 16 * TL;
+                        uint32_t first = 0;
+                        if (have_pre) {
+#pragma unroll
+                            for (int u = 0; u < kPre; u++)
+                                *reinterpret_cast<u64x2*>(dst + 16 * tid + u * st) = pre_v[u] | pre_x[u];
+                            first = kPre;
+                        }
+                        constexpr int kInitPairs = kLoadPairs;
+                        const uint32_t passes = (pairs - first * TL) / (kInitPairs * TL);
+                        uint32_t off = 16 * tid + first * st;
+                        for (uint32_t ps = 0; ps < passes; ps++, off += kInitPairs * st) {
+                            u64x2 v[kInitPairs], x[kInitPairs];
+                            uint32_t o[kInitPairs];
+#pragma unroll
+                            for (int u = 0; u < kInitPairs; u++) {
+                                o[u] = off + u * st;
+                                if (u > 0)
+                                    asm volatile("" : "+v"(o[u]));
+                                v[u] = *reinterpret_cast<const u64x2*>(src + o[u]);
+                                x[u] = *reinterpret_cast<const u64x2*>(src2 + o[u]);
+                            }
+#pragma unroll
+                            for (int u = 0; u < kInitPairs; u++)
+                                *reinterpret_cast<u64x2*>(dst + o[u]) = v[u] | x[u];
+                        }
+                        for (; off < 16 * pairs; off += st)
+                            *reinterpret_cast<u64x2*>(dst + off) =
+                                *reinterpret_cast<const u64x2*>(src + off) |
+                                *reinterpret_cast<const u64x2*>(src2 + off);
+                        if ((L.rw & 1u) && tid == 0) {
+                            const uint32_t o = 8 * (L.rw - 1);
+                            *reinterpret_cast<uint64_t*>(dst + o) =
+                                *reinterpret_cast<const uint64_t*>(src + o) |
+                                *reinterpret_cast<const uint64_t*>(src2 + o);
+                        }
+                        if (gw0 == 0 && L.origin && tid == 0)
+                            bm[0] |= 1ull;
+                    } else {
+                        for (uint32_t w = tid; w < L.rw; w += TL)
+                            bm[w] = (gw0 + (int64_t)w < 0)
+                                        ? ~0ull
+                                        : (reinterpret_cast<const uint64_t*>(src)[w] |
+                                           reinterpret_cast<const uint64_t*>(src2)[w] |
+                                           (gw0 + (int64_t)w == 0 ? (uint64_t)L.origin : 0ull));
+                    }
+                    __syncthreads();
+                    phase_tick(0);
+
+                    // medium primes (both roles), the hit slots (loaders)
+                    mark_medium();
+                    if (L.bucket_cnt) {
+                        if (nb <= cap) {
+                            if (slot_pos < R)
+                                mark(bm32, slot_pos);
+                            const uint32_t* sl = L.bucket_slot + (uint64_t)gs * cap;
+                            for (uint32_t e = tid + TL; e < nb; e += TL) {
+                                const uint32_t pos = sl[e];
+                                if (pos < R)
+                                    mark(bm32, pos);
+                            }
+                        } else {
+                            for (uint32_t pi = L.med_end + tid; pi < IV.pmax_end; pi += TL) {
+                                const uint64_t p = L.primes[pi];
+                                const uint64_t q = p * p;
+                                for (uint64_t pos = first_hit(B1, q); pos < R; pos += q)
+                                    mark(bm32, (uint32_t)pos);
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    phase_tick(1);
+
+                    // the next segment's first kPre pairs per lane, at the
+                    // addresses its init uses
+                    have_pre = seg + 1 < seg0 + nsegs && gw0 + (int64_t)SW >= 0 && pairs / TL >= (uint32_t)kPre;
+                    if (have_pre) {
+                        const int64_t gwn = gw0 + (int64_t)SW;
+                        const uint32_t wbn = wb + wstep >= kWheelPeriod ? wb + wstep - kWheelPeriod : wb + wstep;
+                        const char* sn = reinterpret_cast<const char*>(L.wheel + wbn);
+                        const char* sn2 = reinterpret_cast<const char*>(L.wheel2 + gwn % (int64_t)kWheel2Period);
+#pragma unroll
+                        for (int u = 0; u < kPre; u++) {
+                            uint32_t o = 16 * tid + u * 16 * TL;
+                            if (u > 0)
+                                asm volatile("" : "+v"(o));
+                            pre_v[u] = *reinterpret_cast<const u64x2*>(sn + o);
+                            pre_x[u] = *reinterpret_cast<const u64x2*>(sn2 + o);
+                        }
+                    }
+                    __syncthreads();
+                    phase_tick(2);
+                }
+            } else {
+                const uint32_t sid = tid - TL;
+                for (uint32_t seg = seg0; seg < seg0 + nsegs; seg++) {
+                    phase_tick(-1);
+                    set_priority(seg);
+                    const int64_t B1 = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S - (int64_t)L.origin;
+                    // the medium primes' first hits in the region
+                    if (seg == seg0) {
+                        for (uint32_t i = sid; i < nmed; i += TS) {
+                            const uint32_t q = s_medq[i].x;
+                            const int64_t d = (int64_t)((q - 1) >> 1) - B1;
+                            int64_t f = d % (int64_t)q;
+                            if (f < 0)
+                                f += q;
+                            s_f[i] = (uint32_t)f;
+                        }
+                    } else {
+                        for (uint32_t i = sid; i < nmed; i += TS) {
+                            const uint2 qs = s_medq[i];
+                            const uint32_t f = s_f[i];
+                            s_f[i] = f >= qs.y ? f - qs.y : f + qs.x - qs.y;
+                        }
+                    }
+                    __syncthreads();
+                    phase_tick(0);
+
+                    mark_medium();
+                    __syncthreads();
+                    phase_tick(1);
+
+                    // the segment's output words (as in the single-role loop)
+                    const uint64_t wo0 = (uint64_t)seg * SW;
+                    if (wo0 * 64 + (uint64_t)SW * 64 <= n_bits && (((uintptr_t)IV.out_bits) & 15u) == 0) {
+                        for (uint32_t lw = 2 * sid; lw < SW; lw += 2 * TS) {
+                            const uint64_t w0 = bm[lw], w1 = bm[lw + 1], w2 = bm[lw + 2];
+                            u64x2 o;
+                            o.x = ~(sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0);
+                            o.y = ~(sh ? ((w1 >> sh) | (w2 << (64 - sh))) : w1);
+                            *(g_u64x2*)((g_u64*)IV.out_bits + wo0 + lw) = o;
+                        }
+                    } else {
+                        for (uint32_t lw = sid; lw < SW; lw += TS) {
+                            const uint64_t wo = wo0 + lw;
+                            if (wo * 64 >= n_bits)
+                                break;
+                            const uint64_t lo = bm[lw], hi = bm[lw + 1];
+                            uint64_t out = ~(sh ? ((lo >> sh) | (hi << (64 - sh))) : lo);
+                            const uint64_t rem = n_bits - wo * 64;
+                            if (rem < 64)
+                                out &= (1ull << rem) - 1;
+                            ((g_u64*)IV.out_bits)[wo] = out;
+                        }
+                    }
+                    __syncthreads();
+                    phase_tick(2);
+                }
+            }
+        }
+
+        for (uint32_t seg = seg0; seg < seg0 + nsegs && !split; seg++) {
+            phase_tick(-1);
+            set_priority(seg);
             // the region's words start at odd index Bs (a multiple of 64) for
             // the wheel tables (at the launch's origin); its bit 0 is odd index
             // B1 = Bs - origin
@@ -762,15 +998,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                 const uint32_t sh = IV.out_shift;
                 const uint64_t n_bits = IV.I1 - IV.I0;
                 const uint64_t wo0 = (uint64_t)seg * SW;
+                auto store_pair = [&](uint32_t lw) {
+                    const uint64_t w0 = bm[lw], w1 = bm[lw + 1], w2 = bm[lw + 2];
+                    u64x2 o;
+                    o.x = ~(sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0);
+                    o.y = ~(sh ? ((w1 >> sh) | (w2 << (64 - sh))) : w1);
+                    *(g_u64x2*)((g_u64*)IV.out_bits + wo0 + lw) = o;
+                };
                 if (wo0 * 64 + (uint64_t)SW * 64 <= n_bits && (((uintptr_t)IV.out_bits) & 15u) == 0) {
                     // a whole segment of output: two words per lane, 16-byte stores
-                    for (uint32_t lw = 2 * tid; lw < SW; lw += 2 * T) {
-                        const uint64_t w0 = bm[lw], w1 = bm[lw + 1], w2 = bm[lw + 2];
-                        u64x2 o;
-                        o.x = ~(sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0);
-                        o.y = ~(sh ? ((w1 >> sh) | (w2 << (64 - sh))) : w1);
-                        *reinterpret_cast<u64x2*>(IV.out_bits + wo0 + lw) = o;
-                    }
+                    for (uint32_t lw = 2 * tid; lw < SW; lw += 2 * T)
+                        store_pair(lw);
                 } else {
                     for (uint32_t lw = tid; lw < SW; lw += T) {
                         const uint64_t wo = wo0 + lw;
@@ -782,7 +1020,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         const uint64_t rem = n_bits - wo * 64;
                         if (rem < 64)
                             out &= (1ull << rem) - 1;
-                        IV.out_bits[wo] = out;
+                        ((g_u64*)IV.out_bits)[wo] = out;
                     }
                 }
                 __syncthreads();
@@ -934,7 +1172,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                     // one reservation of popcount(U) list entries per word
                     const uint64_t j0 = j0_of();
                     const unsigned long long c = (unsigned long long)__popcll(U);
-                    atomicAdd(&IV.acc->tail_count, c);
+                    g_add(&IV.acc->tail_count, c);
                     unsigned long long idx = atomicAdd(L.tail_count, c);
                     for (uint64_t x = U; x; idx++) {
                         const int bit = __ffsll((unsigned long long)x) - 1;
@@ -943,7 +1181,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                             L.tail_n[idx] = j0 + (uint64_t)bit;
                             L.tail_iv[idx] = ivi;
                         } else {
-                            atomicOr(&IV.acc->status, no_tail ? (unsigned)ESQ_STATUS_EXCEPTIONS_INCOMPLETE
+                            g_or(&IV.acc->status, no_tail ? (unsigned)ESQ_STATUS_EXCEPTIONS_INCOMPLETE
                                                               : (unsigned)ESQ_STATUS_TAIL_OVERFLOW);
                         }
                     }
@@ -979,7 +1217,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                             D[t] |= spread4((pl[3][t >> 3] >> (4 * (t & 7))) & 15u) << 3;
                     }
                     if (FAST && stage_ok) {
-                        uint8_t* o = IV.out_mink + (As - IV.I0) + (uint64_t)(itw * T + (tid & ~63u)) * 64;
+                        g_u8* o = (g_u8*)IV.out_mink + (As - IV.I0) + (uint64_t)(itw * T + (tid & ~63u)) * 64;
                         switch ((delta + 3) >> 2) {
                         case 0: stage_store_run<0>(s_stage, o, D, lane, delta); break;
                         case 1: stage_store_run<1>(s_stage, o, D, lane, delta); break;
@@ -989,7 +1227,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 1 
                         }
                     } else if (V) {
                         const uint64_t j0 = As + (uint64_t)mw * 64;
-                        store_depths(IV.out_mink + ((int64_t)j0 - (int64_t)IV.I0), D, V);
+                        store_depths((g_u8*)IV.out_mink + ((int64_t)j0 - (int64_t)IV.I0), D, V);
                     }
                 }
             };
@@ -1114,12 +1352,12 @@ __global__ __launch_bounds__(256) void k_tail(Launch L)
         }
         if (threadIdx.x == 0) {
             L.tail_d[idx] = (uint8_t)d;
-            atomicAdd(&IV.acc->deep_hist[d], 1ull);
+            g_add(&IV.acc->deep_hist[d], 1ull);
             const uint32_t top = d ? d : 64u;
             for (uint32_t kk = L.k_lds + 2; kk <= top; kk++)
-                atomicMin(&IV.acc->first[kk], (unsigned long long)j);
+                g_min(&IV.acc->first[kk], (unsigned long long)j);
             if (IV.out_mink)
-                IV.out_mink[j - IV.I0] = (uint8_t)d;
+                ((g_u8*)IV.out_mink)[j - IV.I0] = (uint8_t)d;
         }
     }
 }

@@ -20,7 +20,7 @@ ESQ_RECORDS_CAP = 64
 ESQ_EXCEPTIONS_CAP_MAX = 16384
 ESQ_MAX_HI = 1 << 56
 ESQ_NOALLOC_SCRATCH_MAX = 64 << 20
-ESQ_CEILINGS = 7
+ESQ_CEILINGS = 8
 STATUS_TAIL_OVERFLOW = 1
 STATUS_BUCKET_OVERFLOW = 2
 STATUS_EXCEPTIONS_INCOMPLETE = 4
@@ -203,15 +203,17 @@ def phase_take() -> dict:
 
 
 def measure_ceilings() -> dict:
-    """Measured LDS, VALU and L2 ceilings of the current device
+    """Measured LDS, VALU, L2 and HBM-write ceilings of the current device
     (microbenchmarks): bytes/s of conflict-free ds_write_b64, ds_read_b64,
     ds_or_b32, int32 VALU lane-operations/s of full-rate adds/xors, funnel
-    shifts and popcounts, and bytes/s of 16-byte L2 reads."""
+    shifts and popcounts, bytes/s of 16-byte L2 reads, and bytes/s of
+    16-byte stores streaming to HBM."""
     out = (ctypes.c_double * ESQ_CEILINGS)()
     _check(lib().esq_measure_ceilings(out))
     return {"lds_write_b64_Bps": out[0], "lds_read_b64_Bps": out[1], "lds_or_b32_Bps": out[2],
             "valu_int32_ops_per_s": out[3], "valu_alignbit_ops_per_s": out[4],
-            "valu_bcnt_ops_per_s": out[5], "l2_read_Bps": out[6]}
+            "valu_bcnt_ops_per_s": out[5], "l2_read_Bps": out[6],
+            "hbm_write_Bps": out[7]}
 
 
 def sieve_segment(lo: int, hi: int, out=None, stream=None):

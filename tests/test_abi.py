@@ -70,7 +70,7 @@ def test_measurement_calls_validate_arguments():
     for name, bad in (("sieve_seg_log2", 9), ("sieve_seg_log2", 21), ("phase_clock", 2)):
         with pytest.raises(esq.EsqError):
             esq.set_param(name, bad)
-    assert esq.get_param("sieve_seg_log2") == 19 and esq.get_param("phase_clock") == 0
+    assert esq.get_param("sieve_seg_log2") == 20 and esq.get_param("phase_clock") == 0
 
 
 def test_param_validation():
@@ -79,8 +79,11 @@ def test_param_validation():
         esq.set_param("seg_log2", 25)
     with pytest.raises(esq.EsqError):
         esq.set_param("kh", 0)
-    with pytest.raises(esq.EsqError):
-        esq.set_param("block", 100)
+    for name in ("block", "per_n_block", "sieve_block"):
+        for bad in (0, 100, 2048):
+            with pytest.raises(esq.EsqError):
+                esq.set_param(name, bad)
+    assert (esq.get_param("block"), esq.get_param("per_n_block"), esq.get_param("sieve_block")) == (512, 1024, 1024)
     with pytest.raises(esq.EsqError):
         esq.set_param("no_such_knob", 1)
     assert esq.get_param("no_such_knob") == -1

@@ -2,6 +2,8 @@
 by element on the same seeded inputs; exact equality everywhere (integer
 work).  Sizes here span several segments and a ragged tail; the full-size
 configurations are in test_gpu_fullsize.py."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -13,8 +15,9 @@ from tests.conftest import read_golden
 pytestmark = pytest.mark.gpu
 
 MAX_HI = (1 << 50) + (1 << 33)
-DEFAULTS = dict(seg_log2=18, sieve_seg_log2=19, kh=13, block=512, entry_hits=12, tail_cap=1 << 20,
-                medium_max=4095, bucket_cap=0, items_per_wg=4, stagger=72, priority=1, runs_per_wg=1)
+DEFAULTS = dict(seg_log2=18, sieve_seg_log2=20, kh=13, block=512, per_n_block=1024, sieve_block=1024,
+                entry_hits=12, tail_cap=1 << 20, medium_max=4095, bucket_cap=0, items_per_wg=4, stagger=72,
+                priority=1, runs_per_wg=1)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -28,6 +31,10 @@ def lib_ready():
 
 
 def knobs(**kw):
+    """Set the knobs in kw, the rest to their defaults; a block size given
+    alone applies to the per-n mode too."""
+    if "block" in kw:
+        kw.setdefault("per_n_block", kw["block"])
     for k, v in DEFAULTS.items():
         esq.set_param(k, kw.get(k, v))
 
@@ -58,14 +65,38 @@ def assert_same(g, o, per_n=True):
     (1, 1 << 16), (7, (1 << 16) + 3), (12345, 12345 + 100003),
     ((1 << 30) + 1, (1 << 30) + 200001),
 ])
-@pytest.mark.parametrize("seg_log2", [10, 18, 20])
-def test_sieve_bits_exact(lo, hi, seg_log2):
-    knobs(sieve_seg_log2=seg_log2)
+@pytest.mark.parametrize("seg_log2,block", [(10, 1024), (18, 256), (19, 1024), (20, 1024), (20, 64)])
+def test_sieve_bits_exact(lo, hi, seg_log2, block):
+    knobs(sieve_seg_log2=seg_log2, sieve_block=block)
     m0, n, w = esq.sieve_segment(lo, hi)
     om0, on, ow = oracle.sieve_bits(lo, hi)
     assert (m0 if n else om0, n) == (om0, on)
     if n:
         assert np.array_equal(words_np(w), ow)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(sieve_seg_log2=20, sieve_block=1024, medium_max=11000),
+    dict(sieve_seg_log2=20, sieve_block=128), dict(sieve_seg_log2=14, sieve_block=384),
+    dict(sieve_seg_log2=19, sieve_block=1024, bucket_cap=1), dict(sieve_seg_log2=20, priority=0),
+])
+def test_sieve_role_split_knobs(kw):
+    """Sieve alone with the loader/storer split at several block sizes (also
+    where it does not apply: 384 threads, 6 waves), the largest medium range,
+    and overflowing hit slots, against the oracle: a window above 2^32 of 3
+    segments of 2^20 plus a ragged tail, at an odd start (shifted output)."""
+    knobs(**kw)
+    lo = (1 << 32) + 12345
+    hi = lo + 2 * 3 * (1 << 20) + 2 * 777 + 1
+    m0, n, w = esq.sieve_segment(lo, hi)
+    om0, on, ow = oracle_sieve_cached(lo, hi)
+    assert (m0, n) == (om0, on)
+    assert np.array_equal(words_np(w), ow)
+
+
+@functools.lru_cache(maxsize=4)
+def oracle_sieve_cached(lo, hi):
+    return oracle.sieve_bits(lo, hi)
 
 
 def test_sieve_at_2pow40_exact_and_moebius():
@@ -280,6 +311,8 @@ def test_phase_clock_and_ceilings():
     for k in ("valu_int32_ops_per_s", "valu_alignbit_ops_per_s", "valu_bcnt_ops_per_s"):
         assert 1e12 < c[k] < 1e15, (k, c[k])
     assert 1e12 < c["l2_read_Bps"] < 1e15
+    # streaming writes to a buffer 8x the last-level cache: HBM-bound
+    assert 1e12 < c["hbm_write_Bps"] < 1e13
 
 
 def test_near_the_largest_supported_n():
