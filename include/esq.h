@@ -232,7 +232,8 @@ void esq_batch_destroy(esq_batch *batch);
  *                to the exact tail pass
  *   "block"      threads per workgroup of the segment kernel, summary mode
  *                (64..1024, x64; default 512)
- *   "per_n_block" the same in per-n mode (default 1024)
+ *   "per_n_block" the same in per-n mode for one interval (default 1024;
+ *                per-n batches of several intervals use "block")
  *   "sieve_block" the same for esq_sieve_segment (default 1024)
  *   "entry_hits" target marks per lane-task for medium primes (1..4096)
  *   "tail_cap"   capacity of the per-call list of n unresolved in LDS

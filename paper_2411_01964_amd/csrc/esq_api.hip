@@ -376,10 +376,11 @@ uint32_t medium_end(const Ctx* c, const Params& par)
 }
 
 // Threads per workgroup of the segment kernel in a mode (0 summary, 1 per-n,
-// 2 sieve alone).
-uint32_t block_for(const Params& par, int mode)
+// 2 sieve alone) for a launch of n_iv intervals: per-n batches of many (short)
+// intervals keep the summary block size, which keeps more workgroups resident.
+uint32_t block_for(const Params& par, int mode, uint32_t n_iv)
 {
-    return (uint32_t)(mode == 0 ? par.block : mode == 1 ? par.per_n_block : par.sieve_block);
+    return (uint32_t)(mode == 2 ? par.sieve_block : mode == 1 && n_iv == 1 ? par.per_n_block : par.block);
 }
 
 // The medium-prime tables of the verify geometry for the current knobs (at
@@ -395,7 +396,7 @@ int prebuild_med_table(Ctx* c, const Params& par)
     MedTable* mt = nullptr;
     for (int mode = 0; mode < 2; mode++) {
         const int rc = get_med_table_locked(c, rw, (uint32_t)par.seg_log2, med_end, (uint32_t)par.entry_hits,
-                                            block_for(par, mode), &mt);
+                                            block_for(par, mode, 1), &mt);
         if (rc)
             return rc;
     }
@@ -429,7 +430,7 @@ int plan(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<R
 {
     const uint32_t n_iv = (uint32_t)reqs.size();
     const uint32_t log2S = (uint32_t)(mode == 2 ? par.sieve_seg_log2 : par.seg_log2);
-    const uint32_t blk = block_for(par, mode);
+    const uint32_t blk = block_for(par, mode, n_iv);
     const uint64_t S = 1ull << log2S;
     const uint32_t SW = (uint32_t)(S / 64);
     const uint32_t kmax_eff = kmax ? kmax : 63;
