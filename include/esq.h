@@ -288,9 +288,10 @@ int esq_phase_take(uint64_t *ticks);
  * Measured ceilings of the current device, for the rooflines of the segment
  * kernel (Section 3's sieve is LDS work, its search VALU work, the pattern
  * init L2 reads, the per-n and sieve outputs HBM writes): microbenchmarks of
- * conflict-free LDS operations, of int32 VALU issue, of L2 reads and of HBM
- * writes, eight 256-thread workgroups per CU, best of three timed launches
- * each.  out (host, ESQ_CEILINGS doubles) receives:
+ * conflict-free LDS operations, of int32 VALU issue, of L2 reads (eight
+ * 256-thread workgroups per CU) and of HBM writes (one 16-byte store per
+ * thread over the buffer), best of three timed launches each.  out (host,
+ * ESQ_CEILINGS doubles) receives:
  * [0] ds_write_b64 bytes/s, [1] ds_read_b64 bytes/s, [2] ds_or_b32 bytes/s,
  * int32 VALU lane-operations/s of [3] v_add_u32/v_xor_b32, [4] v_alignbit_b32,
  * [5] v_bcnt_u32_b32, [6] L2 read bytes/s of 16-byte loads over a 1 MiB

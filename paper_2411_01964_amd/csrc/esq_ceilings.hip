@@ -3,11 +3,11 @@
 // int32 VALU issue rate of full-rate operations and of the search's funnel
 // shift and popcount, and the L2 read bandwidth of 16-byte loads over an
 // L2-resident buffer (what the segment init streams from the pattern
-// tables), and the HBM write bandwidth of 16-byte stores streaming over a
-// buffer far larger than the caches (the bound of the per-n and sieve
-// outputs).  Each microbenchmark runs eight 256-thread
-// workgroups per CU (8 waves per SIMD) with the operations in inline assembly,
-// so that none is removed or merged by the compiler.
+// tables), and the HBM write bandwidth of 16-byte stores sweeping a buffer
+// far larger than the caches (the bound of the per-n and sieve outputs).
+// Each LDS, VALU and L2 microbenchmark runs eight 256-thread workgroups per
+// CU (8 waves per SIMD), with the operations in inline assembly where the
+// compiler could otherwise remove or merge them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -195,19 +195,17 @@ __global__ __launch_bounds__(kCeilBlock) void k_ceil_l2(const u32x4c* buf, uint6
     sink[(size_t)blockIdx.x * kCeilBlock + tid] = (uint64_t)(acc.x ^ acc.y ^ acc.z ^ acc.w);
 }
 
-// 16-byte stores over the whole buffer: workgroup b writes its own
-// contiguous chunk of iters 4 KB blocks front to back, every store
-// instruction of a wave covering 1 KB (of the store layouts tried -- grid-
-// strided blocks, non-temporal stores, 2 to 16 workgroups per CU -- the
-// fastest on this chip).  The host sizes iters so that the gridDim chunks
-// fill the buffer exactly.
-__global__ __launch_bounds__(kCeilBlock) void k_ceil_hbm_write(u32x4c* buf, uint32_t iters)
+// 16-byte stores over the whole buffer, one per thread: workgroup b writes
+// the 4 KB block b, so the grid sweeps the buffer front to back in launch
+// order.  Of the store layouts tried (each workgroup streaming its own chunk,
+// grid-strided blocks, non-temporal stores, 2 to 16 resident workgroups of
+// 256 to 1024 threads per CU, 1 to 16 stores per thread) this one-shot grid
+// was the fastest, as fast as a library fill.  The host launches exactly
+// kCeilHbmBytes / 4 KB workgroups.
+__global__ __launch_bounds__(kCeilBlock) void k_ceil_hbm_write(u32x4c* buf)
 {
-    const uint32_t tid = threadIdx.x;
-    const u32x4c v = {tid, blockIdx.x, 0x5a5a5a5au, iters};
-    u32x4c* p = buf + (size_t)blockIdx.x * iters * kCeilBlock;
-    for (uint32_t i = 0; i < iters; i++)
-        p[(size_t)i * kCeilBlock + tid] = v;
+    const u32x4c v = {threadIdx.x, blockIdx.x, 0x5a5a5a5au, 0u};
+    buf[(size_t)blockIdx.x * kCeilBlock + threadIdx.x] = v;
 }
 
 }  // namespace ceil
@@ -247,10 +245,11 @@ extern "C" int esq_measure_ceilings(double* out)
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rc = ESQ_EHIP;
-    // bytes (or lane-operations) per thread per iteration
-    const uint32_t hbm_iters = (uint32_t)(kCeilHbmBytes / ((size_t)grid * kCeilBlock * 16));
+    // bytes (or lane-operations) per launch: per thread per iteration x
+    // iterations x threads; the write ceiling is one store per thread
+    const uint32_t hbm_grid = (uint32_t)(kCeilHbmBytes / (kCeilBlock * 16));
     const double per_iter[kCeilings] = {64.0, 64.0, 32.0, 64.0, 64.0, 64.0, 128.0, 16.0};
-    const uint32_t iters[kCeilings] = {1024, 1024, 1024, 512, 256, 256, 128, hbm_iters};
+    const uint32_t iters[kCeilings] = {1024, 1024, 1024, 512, 256, 256, 128, 1};
     for (int t = 0; t < kCeilings && rc == ESQ_OK; t++) {
         float best = 0.f;
         for (int rep = 0; rep < 4 && rc == ESQ_OK; rep++) {
@@ -273,7 +272,7 @@ extern "C" int esq_measure_ceilings(double* out)
             else if (t == 6)
                 hipLaunchKernelGGL(k_ceil_l2, dim3(grid), dim3(kCeilBlock), 0, s, l2buf, sink, iters[t]);
             else
-                hipLaunchKernelGGL(k_ceil_hbm_write, dim3(grid), dim3(kCeilBlock), 0, s, hbmbuf, iters[t]);
+                hipLaunchKernelGGL(k_ceil_hbm_write, dim3(hbm_grid), dim3(kCeilBlock), 0, s, hbmbuf);
             float ms = 0.f;
             if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -284,7 +283,7 @@ extern "C" int esq_measure_ceilings(double* out)
                 best = ms;
         }
         if (rc == ESQ_OK)
-            out[t] = per_iter[t] * iters[t] * (double)grid * kCeilBlock / (best * 1e-3);
+            out[t] = per_iter[t] * iters[t] * (double)(t == 7 ? hbm_grid : grid) * kCeilBlock / (best * 1e-3);
     }
     if (e0)
         (void)hipEventDestroy(e0);
