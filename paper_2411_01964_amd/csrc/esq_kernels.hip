@@ -626,6 +626,91 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 0 
         // a CU the first-launched would finish far ahead of the last.  Raising
         // the priority of a workgroup with more of its run left keeps them
         // level, and the CU busy until the end.
+        // Step 1 of a segment: the words of the two tables (9, 25, 49 and
+        // 121, 169) ORed into the region whose first word is gw0 (table 1 at
+        // offset wb), by the nl lanes lid < nl, from pair `first` on (the
+        // caller wrote the pairs below first * nl); words below odd index 0
+        // are all marked.  16-byte loads (two words per lane; the tables need
+        // only 8-byte alignment for global loads), 16-byte LDS stores; byte
+        // offsets are 32-bit so that a load is a scalar base plus one lane
+        // offset.
+        auto init_region = [&](int64_t gw0, uint32_t wb, uint32_t lid, uint32_t nl, uint32_t first) {
+            int64_t g2 = gw0 % (int64_t)kWheel2Period;
+            if (g2 < 0)
+                g2 += kWheel2Period;
+            const char* src = reinterpret_cast<const char*>(L.wheel + wb);
+            const char* src2 = reinterpret_cast<const char*>(L.wheel2 + g2);
+            char* dst = reinterpret_cast<char*>(bm);
+            if (gw0 >= 0) {
+                const uint32_t st = 16 * nl;
+                const uint32_t pairs = L.rw / 2;
+                constexpr int kInitPairs = 2;  // pairs per lane in flight (VGPR budget)
+                const uint32_t passes = (pairs - first * nl) / (kInitPairs * nl);
+                uint32_t off = 16 * lid + first * st;
+                for (uint32_t ps = 0; ps < passes; ps++, off += kInitPairs * st) {
+                    u64x2 v[kInitPairs], x[kInitPairs];
+                    uint32_t o[kInitPairs];
+#pragma unroll
+                    for (int u = 0; u < kInitPairs; u++) {
+                        // each pair's offset as its own 32-bit value, so that
+                        // its loads keep the scalar-base form
+                        o[u] = off + u * st;
+                        if (u > 0)
+                            asm volatile("" : "+v"(o[u]));
+                        v[u] = *reinterpret_cast<const u64x2*>(src + o[u]);
+                        x[u] = *reinterpret_cast<const u64x2*>(src2 + o[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kInitPairs; u++)
+                        *reinterpret_cast<u64x2*>(dst + o[u]) = v[u] | x[u];
+                }
+                for (; off < 16 * pairs; off += st)
+                    *reinterpret_cast<u64x2*>(dst + off) =
+                        *reinterpret_cast<const u64x2*>(src + off) |
+                        *reinterpret_cast<const u64x2*>(src2 + off);
+                if ((L.rw & 1u) && lid == 0) {
+                    const uint32_t o = 8 * (L.rw - 1);
+                    *reinterpret_cast<uint64_t*>(dst + o) =
+                        *reinterpret_cast<const uint64_t*>(src + o) |
+                        *reinterpret_cast<const uint64_t*>(src2 + o);
+                }
+                // at origin 1 a region whose first word starts at odd index 0
+                // has bit 0 at odd index -1, not positive: marked (lane 0
+                // wrote word 0 itself)
+                if (gw0 == 0 && L.origin && lid == 0)
+                    bm[0] |= 1ull;
+            } else {
+                // words below odd index 0 are all marked; at origin 1 the word
+                // at index 0 starts with odd index -1, marked too
+                for (uint32_t w = lid; w < L.rw; w += nl)
+                    bm[w] = (gw0 + (int64_t)w < 0)
+                                ? ~0ull
+                                : (reinterpret_cast<const uint64_t*>(src)[w] |
+                                   reinterpret_cast<const uint64_t*>(src2)[w] |
+                                   (gw0 + (int64_t)w == 0 ? (uint64_t)L.origin : 0ull));
+            }
+        };
+        // each medium prime's first hit in the region whose bit 0 is odd index
+        // B1, by the nl lanes lid < nl: from scratch for a run's first segment,
+        // else one segment on from the last
+        auto first_hits = [&](int64_t B1, bool restart, uint32_t lid, uint32_t nl) {
+            if (restart) {
+                for (uint32_t i = lid; i < nmed; i += nl) {
+                    const uint32_t q = s_medq[i].x;
+                    const int64_t d = (int64_t)((q - 1) >> 1) - B1;
+                    int64_t f = d % (int64_t)q;
+                    if (f < 0)
+                        f += q;
+                    s_f[i] = (uint32_t)f;
+                }
+            } else {
+                for (uint32_t i = lid; i < nmed; i += nl) {
+                    const uint2 qs = s_medq[i];
+                    const uint32_t f = s_f[i];
+                    s_f[i] = f >= qs.y ? f - qs.y : f + qs.x - qs.y;
+                }
+            }
+        };
         auto set_priority = [&](uint32_t seg) {
             if (L.priority) {
                 const uint32_t q = min(((seg0 + nsegs - seg) * 4u) / nsegs, 3u);
@@ -651,11 +736,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 0 
         // load the next segment's tables and hit slots.  Both loops meet at
         // the same three barriers per segment.  Needs the task table in LDS
         // and an even number of waves.
-        constexpr uint32_t kLoadQuarters = 2;   // loader share of the waves, in quarters
-        constexpr int kLoadPairs = 2;           // table pairs per loader lane in flight
-        const bool split = MODE == 2 && L.tasks_in_lds && (T * kLoadQuarters / 4) % 64 == 0;
+        const bool split = MODE == 2 && L.tasks_in_lds && T % 128 == 0;
         if (split) {
-            const uint32_t TL = T * kLoadQuarters / 4, TS = T - TL;
+            const uint32_t TL = T / 2, TS = T - TL;
             // wave-uniform (TL is a multiple of 64), and known to be so: each
             // wave runs exactly one of the two loops
             const bool loader = rfl(tid) < TL;
@@ -690,59 +773,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 0 
                         if (nb <= cap && tid < nb)
                             slot_pos = L.bucket_slot[(uint64_t)gs * cap + tid];
                     }
-                    int64_t g2 = gw0 % (int64_t)kWheel2Period;
-                    if (g2 < 0)
-                        g2 += kWheel2Period;
-                    const char* src = reinterpret_cast<const char*>(L.wheel + wb);
-                    const char* src2 = reinterpret_cast<const char*>(L.wheel2 + g2);
-                    char* dst = reinterpret_cast<char*>(bm);
-                    if (gw0 >= 0) {
-                        const uint32_t st = 16 * TL;
-                        uint32_t first = 0;
-                        if (have_pre) {
+                    uint32_t first = 0;  // pairs per lane fetched a segment ahead
+                    if (have_pre && gw0 >= 0) {
 #pragma unroll
-                            for (int u = 0; u < kPre; u++)
-                                *reinterpret_cast<u64x2*>(dst + 16 * tid + u * st) = pre_v[u] | pre_x[u];
-                            first = kPre;
-                        }
-                        constexpr int kInitPairs = kLoadPairs;
-                        const uint32_t passes = (pairs - first * TL) / (kInitPairs * TL);
-                        uint32_t off = 16 * tid + first * st;
-                        for (uint32_t ps = 0; ps < passes; ps++, off += kInitPairs * st) {
-                            u64x2 v[kInitPairs], x[kInitPairs];
-                            uint32_t o[kInitPairs];
-#pragma unroll
-                            for (int u = 0; u < kInitPairs; u++) {
-                                o[u] = off + u * st;
-                                if (u > 0)
-                                    asm volatile("" : "+v"(o[u]));
-                                v[u] = *reinterpret_cast<const u64x2*>(src + o[u]);
-                                x[u] = *reinterpret_cast<const u64x2*>(src2 + o[u]);
-                            }
-#pragma unroll
-                            for (int u = 0; u < kInitPairs; u++)
-                                *reinterpret_cast<u64x2*>(dst + o[u]) = v[u] | x[u];
-                        }
-                        for (; off < 16 * pairs; off += st)
-                            *reinterpret_cast<u64x2*>(dst + off) =
-                                *reinterpret_cast<const u64x2*>(src + off) |
-                                *reinterpret_cast<const u64x2*>(src2 + off);
-                        if ((L.rw & 1u) && tid == 0) {
-                            const uint32_t o = 8 * (L.rw - 1);
-                            *reinterpret_cast<uint64_t*>(dst + o) =
-                                *reinterpret_cast<const uint64_t*>(src + o) |
-                                *reinterpret_cast<const uint64_t*>(src2 + o);
-                        }
-                        if (gw0 == 0 && L.origin && tid == 0)
-                            bm[0] |= 1ull;
-                    } else {
-                        for (uint32_t w = tid; w < L.rw; w += TL)
-                            bm[w] = (gw0 + (int64_t)w < 0)
-                                        ? ~0ull
-                                        : (reinterpret_cast<const uint64_t*>(src)[w] |
-                                           reinterpret_cast<const uint64_t*>(src2)[w] |
-                                           (gw0 + (int64_t)w == 0 ? (uint64_t)L.origin : 0ull));
+                        for (int u = 0; u < kPre; u++)
+                            *reinterpret_cast<u64x2*>(reinterpret_cast<char*>(bm) + 16 * (tid + u * TL)) =
+                                pre_v[u] | pre_x[u];
+                        first = kPre;
                     }
+                    init_region(gw0, wb, tid, TL, first);
                     __syncthreads();
                     phase_tick(0);
 
@@ -796,23 +835,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 0 
                     phase_tick(-1);
                     set_priority(seg);
                     const int64_t B1 = IV.A0 - (int64_t)HW * 64 + (int64_t)seg * (int64_t)S - (int64_t)L.origin;
-                    // the medium primes' first hits in the region
-                    if (seg == seg0) {
-                        for (uint32_t i = sid; i < nmed; i += TS) {
-                            const uint32_t q = s_medq[i].x;
-                            const int64_t d = (int64_t)((q - 1) >> 1) - B1;
-                            int64_t f = d % (int64_t)q;
-                            if (f < 0)
-                                f += q;
-                            s_f[i] = (uint32_t)f;
-                        }
-                    } else {
-                        for (uint32_t i = sid; i < nmed; i += TS) {
-                            const uint2 qs = s_medq[i];
-                            const uint32_t f = s_f[i];
-                            s_f[i] = f >= qs.y ? f - qs.y : f + qs.x - qs.y;
-                        }
-                    }
+                    first_hits(B1, seg == seg0, sid, TS);
                     __syncthreads();
                     phase_tick(0);
 
@@ -872,81 +895,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MODE == 0 
             }
 
             // 1. the wheel: odd multiples of 9, 25, 49 and of 121, 169 from the
-            //    two tables (words below odd index 0 are all marked); each
-            //    medium prime's first hit in the region.  Byte offsets are
-            //    32-bit so that a load is a scalar base plus one lane offset.
-            int64_t g2 = gw0 % (int64_t)kWheel2Period;
-            if (g2 < 0)
-                g2 += kWheel2Period;
-            const char* src = reinterpret_cast<const char*>(L.wheel + wb);
-            const char* src2 = reinterpret_cast<const char*>(L.wheel2 + g2);
-            char* dst = reinterpret_cast<char*>(bm);
-            if (gw0 >= 0) {
-                // 16-byte loads (two words per lane; the tables need only
-                // 8-byte alignment for global loads), 16-byte LDS stores
-                const uint32_t st = 16 * T;
-                const uint32_t pairs = L.rw / 2;
-                constexpr int kInitPairs = 2;  // pairs per lane in flight (VGPR budget)
-                const uint32_t passes = pairs / (kInitPairs * T);
-                uint32_t off = 16 * tid;
-                for (uint32_t ps = 0; ps < passes; ps++, off += kInitPairs * st) {
-                    u64x2 v[kInitPairs], x[kInitPairs];
-                    uint32_t o[kInitPairs];
-#pragma unroll
-                    for (int u = 0; u < kInitPairs; u++) {
-                        // each pair's offset as its own 32-bit value, so that
-                        // its loads keep the scalar-base form
-                        o[u] = off + u * st;
-                        if (u > 0)
-                            asm volatile("" : "+v"(o[u]));
-                        v[u] = *reinterpret_cast<const u64x2*>(src + o[u]);
-                        x[u] = *reinterpret_cast<const u64x2*>(src2 + o[u]);
-                    }
-#pragma unroll
-                    for (int u = 0; u < kInitPairs; u++)
-                        *reinterpret_cast<u64x2*>(dst + o[u]) = v[u] | x[u];
-                }
-                for (; off < 16 * pairs; off += st)
-                    *reinterpret_cast<u64x2*>(dst + off) =
-                        *reinterpret_cast<const u64x2*>(src + off) |
-                        *reinterpret_cast<const u64x2*>(src2 + off);
-                if ((L.rw & 1u) && tid == 0) {
-                    const uint32_t o = 8 * (L.rw - 1);
-                    *reinterpret_cast<uint64_t*>(dst + o) =
-                        *reinterpret_cast<const uint64_t*>(src + o) |
-                        *reinterpret_cast<const uint64_t*>(src2 + o);
-                }
-                // at origin 1 a region whose first word starts at odd index 0
-                // has bit 0 at odd index -1, not positive: marked (thread 0
-                // wrote word 0 itself)
-                if (gw0 == 0 && L.origin && tid == 0)
-                    bm[0] |= 1ull;
-            } else {
-                // words below odd index 0 are all marked; at origin 1 the word
-                // at index 0 starts with odd index -1, marked too
-                for (uint32_t w = tid; w < L.rw; w += T)
-                    bm[w] = (gw0 + (int64_t)w < 0)
-                                ? ~0ull
-                                : (reinterpret_cast<const uint64_t*>(src)[w] |
-                                   reinterpret_cast<const uint64_t*>(src2)[w] |
-                                   (gw0 + (int64_t)w == 0 ? (uint64_t)L.origin : 0ull));
-            }
-            if (seg == seg0) {
-                for (uint32_t i = tid; i < nmed; i += T) {
-                    const uint32_t q = s_medq[i].x;
-                    const int64_t d = (int64_t)((q - 1) >> 1) - B1;
-                    int64_t f = d % (int64_t)q;
-                    if (f < 0)
-                        f += q;
-                    s_f[i] = (uint32_t)f;
-                }
-            } else {
-                for (uint32_t i = tid; i < nmed; i += T) {
-                    const uint2 qs = s_medq[i];
-                    const uint32_t f = s_f[i];
-                    s_f[i] = f >= qs.y ? f - qs.y : f + qs.x - qs.y;
-                }
-            }
+            //    two tables; each medium prime's first hit in the region
+            init_region(gw0, wb, tid, T, 0);
+            first_hits(B1, seg == seg0, tid, T);
             __syncthreads();
             phase_tick(0);
 
