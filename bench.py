@@ -122,8 +122,8 @@ def host_info():
 
 
 def oracle_threads(host):
-    """Threads for the oracle: every core the process may use, at most the 16
-    host cores a one-GPU machine grants to one GPU."""
+    """Threads for the oracle: every core the process may use, at most 16 (one
+    GPU's share of the host cores of an eight-GPU node)."""
     return max(1, min(16, host["affinity"]))
 
 
