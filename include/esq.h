@@ -23,8 +23,13 @@
  *     device-accessible memory (hipMalloc'd, a torch CUDA tensor, or pinned
  *     host memory from hipHostMalloc).  The caller owns and frees every
  *     output buffer; the library never frees caller memory.  The library owns
- *     the resident prime table, the pattern table and per-call scratch
- *     (allocated and released in stream order on the caller's stream).
+ *     the resident prime table, the pattern table and per-call scratch.
+ *     Scratch comes from blocks the library keeps for reuse (at most 16,
+ *     4 GiB in all, per device, held until esq_shutdown): a call takes the
+ *     block its stream used last, or another one after making its stream
+ *     wait (on the device) for that block's last use; when none serves, or
+ *     the stream is capturing a graph, it is allocated and released in stream
+ *     order from a memory pool on the caller's stream.
  *   - Asynchrony: calls only enqueue work on `stream` (a hipStream_t; NULL =
  *     the default stream) and return.  Outputs are valid once the stream has
  *     been synchronised.  Calls on different streams may overlap.
@@ -184,7 +189,7 @@ int esq_verify_batch(uint32_t count, const uint64_t *lo, const uint64_t *hi, uin
 
 /*
  * Device scratch, in bytes, that one esq_verify_batch call over these
- * intervals takes from the library's memory pool while it runs: per-segment
+ * intervals holds while it runs (a kept block or pool memory): per-segment
  * hit slots of the large primes, the list of n left to the exact tail pass,
  * per-interval descriptors and accumulators.  The caller's outputs
  * (summaries, records, per-n bytes) are not included.  For count = 1 it is

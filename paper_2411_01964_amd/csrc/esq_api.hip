@@ -71,6 +71,23 @@ struct MedTable {
     uint32_t n_tasks = 0;
 };
 
+// A device block of per-call scratch kept by the library.  A call takes the
+// block its stream used last (else one no call holds whose last use has
+// completed on the device, else a new one), makes its stream wait for the
+// block's last use (an event: nothing to wait for on the same stream), and
+// records that event after its kernels.  Stream-ordered pool allocation and
+// release of the same sizes blocked the host for about as long as a call's
+// kernels run, so that the host could not queue calls ahead of the device.
+struct ScratchBlock {
+    char* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t last = nullptr;      // recorded after each call that used the block
+    hipStream_t stream = nullptr;   // the stream of that call
+    bool taken = false;             // held by a call being enqueued
+};
+constexpr size_t kScratchBlocks = 16;
+constexpr size_t kScratchCacheBytes = (size_t)4 << 30;
+
 struct Ctx {
     int device = -1;
     int n_cu = 256;
@@ -87,7 +104,10 @@ struct Ctx {
     uint64_t* d_wheel2 = nullptr;
     uint64_t* d_wheel_s = nullptr;  // the two tables one position lower (search regions)
     uint64_t* d_wheel2_s = nullptr;
-    hipMemPool_t pool = nullptr;    // per-call scratch: stream-ordered, kept cached
+    hipMemPool_t pool = nullptr;    // per-call scratch when no cached block serves (stream-ordered)
+    std::vector<ScratchBlock> scratch;  // per-call scratch blocks kept for reuse (under scr_mu)
+    size_t scratch_bytes = 0;
+    std::mutex scr_mu;
     std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint32_t>, MedTable> med;
     std::map<std::tuple<int, uint32_t, size_t>, int> occupancy;  // (mode, block, LDS bytes) -> workgroups per CU
     uint64_t generation = 0;        // changes whenever a device table that a prepared batch holds is replaced
@@ -246,10 +266,14 @@ void free_ctx(Ctx* c)
         (void)hipFree(c->d_primes);
     if (c->d_wheel)
         (void)hipFree(c->d_wheel);  // d_wheel2 lives in the same allocation
-    if (c->pool) {
-        (void)hipDeviceSynchronize();  // no call may still hold pool memory
-        (void)hipMemPoolDestroy(c->pool);
+    if (c->pool || !c->scratch.empty())
+        (void)hipDeviceSynchronize();  // no call may still hold scratch
+    for (ScratchBlock& b : c->scratch) {
+        (void)hipFree(b.p);
+        (void)hipEventDestroy(b.last);
     }
+    if (c->pool)
+        (void)hipMemPoolDestroy(c->pool);
     delete c;
 }
 
@@ -772,7 +796,72 @@ int launch_seq(const Planned& P, bool iv_by_value, bool profile, void* out_summa
     return ESQ_OK;
 }
 
-// Plan, allocate in stream order, upload, enqueue, release in stream order.
+// A cached scratch block of at least `bytes` for a call on stream s (see
+// ScratchBlock), with s made to wait for the block's last use; -1 when none
+// can be had (every block held or too small and the cache full, an
+// allocation failure, or s capturing a graph): the caller then allocates from
+// the pool.
+int scratch_take(Ctx* c, size_t bytes, hipStream_t s, char** ptr)
+{
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap_status) != hipSuccess || cap_status != hipStreamCaptureStatusNone)
+        return -1;
+    int idx = -1;
+    hipEvent_t wait = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c->scr_mu);
+        std::vector<ScratchBlock>& v = c->scratch;
+        for (size_t i = 0; i < v.size() && idx < 0; i++)
+            if (!v[i].taken && v[i].stream == s && v[i].cap >= bytes)
+                idx = (int)i;
+        for (size_t i = 0; i < v.size() && idx < 0; i++)
+            if (!v[i].taken && v[i].cap >= bytes && hipEventQuery(v[i].last) == hipSuccess)
+                idx = (int)i;
+        if (idx < 0) {
+            if (v.size() >= kScratchBlocks || c->scratch_bytes + bytes > kScratchCacheBytes)
+                return -1;
+            ScratchBlock b;
+            b.cap = (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+            if (hipMalloc((void**)&b.p, b.cap) != hipSuccess) {
+                (void)hipGetLastError();
+                return -1;
+            }
+            if (hipEventCreateWithFlags(&b.last, hipEventDisableTiming) != hipSuccess) {
+                (void)hipFree(b.p);
+                return -1;
+            }
+            c->scratch_bytes += b.cap;
+            v.push_back(b);
+            idx = (int)v.size() - 1;
+        }
+        v[idx].taken = true;
+        *ptr = v[idx].p;
+        // the per-thread stream handle names another stream on each thread
+        if (v[idx].stream != s || s == hipStreamPerThread)
+            wait = v[idx].last;
+    }
+    // the block's last use, on another stream, completes before this call's
+    // kernels (a block never used has an unrecorded event: no wait)
+    if (wait && hipStreamWaitEvent(s, wait, 0) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(c->scr_mu);
+        c->scratch[idx].taken = false;
+        return -1;
+    }
+    return idx;
+}
+
+// Hand block idx back after a call on stream s has enqueued its kernels.
+void scratch_give(Ctx* c, int idx, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(c->scr_mu);
+    ScratchBlock& b = c->scratch[idx];
+    (void)hipEventRecord(b.last, s);
+    b.stream = s;
+    b.taken = false;
+}
+
+// Plan, take scratch (a cached block or stream-ordered pool memory), upload,
+// enqueue, hand the scratch back in stream order.
 int enqueue(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vector<Req>& reqs,
             void* out_summaries, void* out_records, uint64_t* out_exceptions, uint64_t exc_cap,
             hipStream_t s)
@@ -782,9 +871,18 @@ int enqueue(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vecto
     if (rc)
         return rc;
     char* base = nullptr;
-    hipError_t e = hipMallocFromPoolAsync((void**)&base, P.bytes, c->pool, s);
-    if (e != hipSuccess || !base)
-        return fail(ESQ_ENOMEM, std::string("hipMallocFromPoolAsync(scratch): ") + hipGetErrorString(e));
+    const int blk = scratch_take(c, P.bytes, s, &base);
+    if (blk < 0) {
+        hipError_t e = hipMallocFromPoolAsync((void**)&base, P.bytes, c->pool, s);
+        if (e != hipSuccess || !base)
+            return fail(ESQ_ENOMEM, std::string("hipMallocFromPoolAsync(scratch): ") + hipGetErrorString(e));
+    }
+    auto release = [&]() {
+        if (blk >= 0)
+            scratch_give(c, blk, s);
+        else
+            (void)hipFreeAsync(base, s);
+    };
     bind(&P, base);
     const bool by_value = P.ivs.size() == 1;
     if (!by_value) {
@@ -797,13 +895,13 @@ int enqueue(Ctx* c, const Params& par, int mode, uint32_t kmax, const std::vecto
             dsts.push_back(base + P.o_items);
         }
         if ((rc = stage_upload(parts, dsts, s))) {
-            (void)hipFreeAsync(base, s);
+            release();
             return rc;
         }
     }
     rc = launch_seq(P, by_value, par.profile != 0, out_summaries, out_records, out_exceptions,
                     exc_cap, s);
-    (void)hipFreeAsync(base, s);
+    release();
     return rc;
 }
 

@@ -275,6 +275,28 @@ def test_table3_windows():
         assert g["n_exceptions"] == 0
 
 
+def test_calls_on_several_streams_share_scratch_blocks_safely():
+    """Per-call scratch blocks are reused by later calls on the same stream
+    and, after a device-side wait, by calls on other streams: many calls of
+    three sizes (summary and per-n) enqueued over four streams without
+    synchronising all equal the same calls made one at a time."""
+    knobs()
+    ivs = [((1 << 44) + 1, (1 << 44) + (1 << 24)), ((1 << 40) + 7, (1 << 40) + (1 << 20) + 3),
+           (3, 1 << 21)]
+    ref = [esq.verify_range(a, b, per_n=True) for a, b in ivs]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    pend = []
+    for i in range(24):
+        a, b = ivs[(i * 7) % 3]
+        pend.append((ivs.index((a, b)), esq.verify_range_async(a, b, per_n=(i % 5 == 0),
+                                                               stream=streams[i % 4])))
+    for j, p in pend:
+        r = p.result()
+        assert r["hist"] == ref[j]["hist"] and r["records"] == ref[j]["records"]
+        if "per_n" in r:
+            assert torch.equal(r["per_n"], ref[j]["per_n"])
+
+
 def test_errors_are_reported():
     with pytest.raises(esq.EsqError):
         esq.verify_range(3, 100, kmax=64)
