@@ -81,10 +81,12 @@ def test_sieve_bits_exact(lo, hi, seg_log2, block):
     dict(sieve_seg_log2=19, sieve_block=1024, bucket_cap=1), dict(sieve_seg_log2=20, priority=0),
 ])
 def test_sieve_role_split_knobs(kw):
-    """Sieve alone with the loader/storer split at several block sizes (also
-    where it does not apply: 384 threads, 6 waves), the largest medium range,
-    and overflowing hit slots, against the oracle: a window above 2^32 of 3
-    segments of 2^20 plus a ragged tail, at an odd start (shifted output)."""
+    """Sieve alone with the loader/storer split at several block sizes (2 to
+    16 waves; 384 threads: three loader and three storer waves), the largest
+    medium range, and overflowing hit slots, against the oracle: a window
+    above 2^32 of 3 segments of 2^20 plus a ragged tail, at an odd start
+    (shifted output).  The single-role loop (64 threads) is in
+    test_sieve_bits_exact."""
     knobs(**kw)
     lo = (1 << 32) + 12345
     hi = lo + 2 * 3 * (1 << 20) + 2 * 777 + 1
